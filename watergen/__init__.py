@@ -1,0 +1,13 @@
+"""Seeded synthetic inputs shaped like the paper's water-cluster matrices.
+
+Shared by the oracle, the tests and the benchmark; it contains no part of the
+SpAMM or SP2 arithmetic.
+"""
+from .cluster import (BASIS_PER_MOLECULE, OCC_PER_MOLECULE, Request, WaterCluster,
+                      lattice_sites, molecule_centres, request_seed, request_stream,
+                      water_cluster)
+from .hilbert import hilbert_index, transpose_index
+
+__all__ = ["BASIS_PER_MOLECULE", "OCC_PER_MOLECULE", "Request", "WaterCluster",
+           "lattice_sites", "molecule_centres", "request_seed", "request_stream",
+           "water_cluster", "hilbert_index", "transpose_index"]
