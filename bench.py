@@ -1,0 +1,210 @@
+#!/usr/bin/env python3
+"""Benchmark of SpAMM inside SP2 on one MI355X.
+
+Workload: the 150-molecule synthetic water cluster (N = 3750, padded to
+4096, 32 x 32 leaf blocks, decay length 1.5 A, seed 0), FP32 leaf products.
+One step is one full sp2_solve at tau = 1e-6 with F resident on the device
+and P written to device memory: Gershgorin scaling, tree build, and every
+SP2 iteration's occlusion pass, leaf products with the fused SP2 update,
+norm pyramid and FP64 decisions, then the dense read-back.
+
+Printed: one JSON line.  `value` is the SpAMM effective rate over the timed
+solves, 65,536 flop per executed 32x32x32 leaf product divided by wall time.
+Also reported: SP2 solves/s and p50/p99 solve latency, spamm_multiply of
+X_0 * X_0 at tau in {1e-8, 1e-6, 1e-4}, the roofline of the leaf-product
+kernel from HIP events recorded around each of its launches, and the FP64
+oracle timed on the host cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+LEAF_FLOP = 2 * 32 ** 3            # one 32x32x32 leaf product
+PEAK_FP32_TFLOPS = 157.3           # MI355X dense FP32 matrix peak
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+GEMM_SOURCE = os.path.join(ROOT, "paper_1403_7458_amd", "csrc", "leafgemm.hip")
+
+
+def source_sha(path: str) -> str:
+    with open(path, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """Per-dispatch HBM bytes of `kernel` from the committed rocprofv3 counter
+    summary, or None when missing or taken from a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            data = json.load(fh)
+        ent = data[kernel][workload]
+    except (OSError, KeyError, ValueError):
+        return None
+    if ent.get("source_sha") != source_sha(GEMM_SOURCE):
+        return None
+    return ent.get("bytes_per_dispatch")
+
+
+def percentile(xs, q):
+    return float(np.percentile(np.asarray(xs), q)) if xs else None
+
+
+def cpu_baseline(x0: np.ndarray, tau: float, budget_s: float = 12.0):
+    """The FP64 oracle's recursive task form (Alg. 1, OpenMP, all host cores)
+    on X_0 * X_0: effective GFLOP/s over repeats filling about budget_s."""
+    from oracle import alg1
+    times, n_exec = [], 0
+    t_start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        _, info = alg1.spamm_alg1(x0, x0, tau)
+        times.append(time.perf_counter() - t0)
+        n_exec = info["n_exec"]
+        if time.perf_counter() - t_start > budget_s or len(times) >= 30:
+            break
+    t = float(np.median(times))
+    return {"value": LEAF_FLOP * n_exec / t / 1e9, "unit": "GFLOP/s",
+            "cores": int(alg1.max_threads()), "kind": "oracle",
+            "sample": f"{len(times)} x SpAMM X_0*X_0 (tau={tau:g}, {n_exec} leaf products, "
+                      f"FP64, recursive task form), median {t:.3f} s each"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--tau", type=float, default=1e-6)
+    ap.add_argument("--molecules", type=int, default=150)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-multiply", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the SpAMM/SP2 path "
+              "is single-device here and has no multi-GPU form to measure.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1403_7458_amd as sp
+    from watergen import water_cluster
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    sp.load()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    w = water_cluster(args.molecules, 1.5, 0)
+    n, n_occ, tau = w.n, w.n_occ, args.tau
+    f = torch.from_numpy(w.f).to(dev)
+    p = torch.empty_like(f)
+
+    def solve():
+        return sp.sp2_solve(f, n_occ, tau, out=p, precision="fp32", stream=stream)
+
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    sp.profile_reset()
+    sp.profile_enable(True)
+    lat, stats = [], None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        _, stats = solve()
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    sp.profile_enable(False)
+    prof = sp.profile_read()
+
+    execs = stats["n_exec_total"]
+    value = LEAF_FLOP * execs * args.steps / elapsed / 1e9
+    # Accuracy of the last result (measurement only): trace and idempotency.
+    pt = p.double()
+    tr_err = abs(float(torch.trace(pt)) - n_occ)
+    idem = float(torch.linalg.norm(pt @ pt - pt))
+
+    # Roofline of the leaf-product kernel: algorithmic flop per launch over
+    # the mean launch duration from the events bracketing each launch.
+    launches = prof["launches"]["gemm"]
+    gemm_ms = prof["ms"]["gemm"] / max(launches, 1)
+    per_launch = prof["gemm_products"] / max(launches, 1)
+    achieved = LEAF_FLOP * per_launch / (gemm_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": measured_traffic("leaf_gemm_f32", f"water{args.molecules}_tau{tau:g}"),
+                "kernel": "k_leaf_gemm_f32 (fused SP2 update)",
+                "launches": launches, "mean_launch_ms": round(gemm_ms, 4),
+                "products_per_launch": round(per_launch, 1)}
+    phase_ms = {k: round(v / args.steps, 3) for k, v in prof["ms"].items()}
+
+    multiply = {}
+    x0 = None
+    if not args.no_multiply:
+        mx, lo, hi = sp.sp2_initial_guess(f, "fp32", stream=stream)
+        for t in (1e-8, 1e-6, 1e-4):
+            sp.spamm_multiply(mx, mx, t, stream=stream)
+            times, st = [], None
+            for _ in range(5):
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                mc, st = sp.spamm_multiply(mx, mx, t, stream=stream)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - ts)
+                mc.close()
+            tm = float(np.median(times))
+            multiply[f"{t:g}"] = {
+                "gflops": round(LEAF_FLOP * st["n_exec"] / tm / 1e9, 1), "ms": round(tm * 1e3, 3),
+                "n_exec": st["n_exec"], "culled_frac_nonzero": round(1 - st["n_exec"] / st["n_nonzero_pairs"], 4),
+                "culled_frac_dense": round(1 - st["n_exec"] / st["n_dense"], 4),
+                "err_bound": st["err_bound"]}
+        mx.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import sp2_oracle as sp2o
+        from oracle import spamm_oracle as so
+        lo, hi = sp2o.gershgorin(w.f)
+        x0 = sp2o.initial_x(w.f, lo, hi, so.padded_size(n))
+        cpu = cpu_baseline(x0, tau)
+
+    line = {
+        "metric": "SpAMM effective GFLOP/s & SP2 solves/sec at tau=1e-6; p50/p99 solve latency",
+        "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"sp2_solve water cluster {args.molecules} molecules "
+                               f"(N={n}, padded {32 * (1 << int(np.ceil(np.log2(n / 32))))}), "
+                               f"decay 1.5 A, seed 0, fp32 leaves, tau={tau:g}",
+                   "molecules": args.molecules, "n": n, "n_occ": n_occ, "tau": tau,
+                   "leaf": 32, "precision": "fp32"},
+        "sp2_solves_per_s": round(args.steps / elapsed, 3),
+        "latency_ms": {"p50": round(percentile(lat, 50) * 1e3, 3),
+                       "p99": round(percentile(lat, 99) * 1e3, 3)},
+        "sp2": {"iterations": stats["iterations"], "stop": stats["stop"],
+                "leaf_products": execs, "trace_error": tr_err, "idempotency": idem},
+        "phase_ms_per_step": phase_ms,
+        "multiply": multiply,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

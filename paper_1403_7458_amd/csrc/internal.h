@@ -1,0 +1,250 @@
+// Internal declarations shared by the translation units of libspamm.
+// Device layout of a SpAMM matrix (one per handle):
+//   pool    tiles of 32 x 32 elements in the working precision, each tile
+//           contiguous and row-major; tile s holds block coords[s]
+//   map     int32[nb * nb], row-major over (i, j): tile slot or -1
+//   coords  int32[cap], slot -> (i << 16) | j
+//   norms   FP64 Frobenius norms of every quadtree tier; tier t is a
+//           2^t x 2^t row-major array at offset (4^t - 1) / 3 (Eqs. 2-3)
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/spamm.h"
+
+namespace spamm {
+
+constexpr int kLeaf = 32;
+constexpr int kLeaf2 = kLeaf * kLeaf;
+constexpr int kMaxTiers = SPAMM_MAX_DEPTH + 1;
+
+__host__ __device__ inline int64_t tier_offset(int t) { return ((int64_t(1) << (2 * t)) - 1) / 3; }
+inline int64_t norms_size(int depth) { return tier_offset(depth + 1); }
+inline size_t elem_bytes(int prec) { return prec == SPAMM_FP64 ? 8 : 4; }
+inline size_t tile_bytes(int prec) { return kLeaf2 * elem_bytes(prec); }
+
+__host__ __device__ inline int32_t pack_ij(int i, int j) { return (i << 16) | j; }
+__host__ __device__ inline int unpack_i(int32_t p) { return p >> 16; }
+__host__ __device__ inline int unpack_j(int32_t p) { return p & 0xffff; }
+
+// Error carried from a failing step to the C ABI.
+struct Error {
+  int code = SPAMM_OK;
+  std::string msg;
+  bool ok() const { return code == SPAMM_OK; }
+};
+
+Error hip_error(hipError_t e, const char* what);
+#define SPAMM_HIP(call)                                    \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return ::spamm::hip_error(e_, #call); \
+  } while (0)
+#define SPAMM_TRY(expr)               \
+  do {                                \
+    ::spamm::Error r_ = (expr);       \
+    if (!r_.ok()) return r_;          \
+  } while (0)
+
+// Stream-ordered device allocation (hipMallocAsync on the device's default
+// pool, kept cached between calls).
+Error dev_alloc(void** p, size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+template <class T>
+Error dev_alloc_n(T** p, int64_t n, hipStream_t s) {
+  return dev_alloc(reinterpret_cast<void**>(p), size_t(n > 0 ? n : 1) * sizeof(T), s);
+}
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  Error reserve(size_t want, hipStream_t s);
+  void release(hipStream_t s);
+};
+
+// Kernel timing (phase totals over HIP events).
+struct PhaseTimer {
+  int phase;
+  hipStream_t stream;
+  hipEvent_t start = nullptr;
+  int64_t products;
+  PhaseTimer(int ph, hipStream_t s, int64_t prod = 0);
+  ~PhaseTimer();
+};
+bool profiling_on();
+
+}  // namespace spamm
+
+// The matrix handle.
+struct spamm_matrix {
+  int64_t n = 0, n_pad = 0;
+  int nb = 0, depth = 0, prec = SPAMM_FP32;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int64_t n_blocks = 0;
+  int64_t cap_blocks = 0;
+  void* pool = nullptr;
+  int32_t* map = nullptr;
+  int32_t* coords = nullptr;
+  double* norms = nullptr;
+  double frob = 0.0;
+};
+
+namespace spamm {
+
+// ---- tree.hip --------------------------------------------------------------
+
+// Scaling applied while ingesting: value = (diag * [i == j] + sign * a_ij) / div
+// for i, j < n, zero in the padding.  Lives in device memory so that SP2's
+// Gershgorin bounds never leave the device before the tiles are written.
+struct Scale {
+  double diag, sign, div;
+  double eps_min, eps_max;
+  double max_abs, max_asym;
+  int32_t nonfinite;
+  int32_t bad_bounds;
+};
+
+Error new_matrix(int64_t n, int prec, hipStream_t s, spamm_matrix** out);
+void free_matrix(spamm_matrix* m);
+Error alloc_pool(spamm_matrix* m, int64_t cap_blocks, hipStream_t s);
+
+// Leaf norms of the scaled input into m->norms (leaf tier), the non-finite
+// flag into scale->nonfinite.  a: device, n x n, lda.
+void launch_leaf_norms_dense(const double* a, int64_t lda, const spamm_matrix* m,
+                             Scale* scale, hipStream_t s);
+// Slots for the blocks with non-zero norm: fills m->map and m->coords
+// (capacity nb*nb) and writes the count into *count_dev.
+Error compact_nonzero_blocks(spamm_matrix* m, int64_t* count_dev, hipStream_t s);
+// Scaled, converted tiles of every stored block; diagonal-block traces of
+// the stored values into trace_part[nb] when non-NULL.
+void launch_write_tiles(const double* a, int64_t lda, const spamm_matrix* m, const Scale* scale,
+                        double* trace_part, hipStream_t s);
+// Tier norms above the leaves (Eq. 3).
+void launch_pyramid(const spamm_matrix* m, hipStream_t s);
+// Gershgorin bounds, max |F| and the non-finite flag, then the scale of
+// X_0 = (eps_max I - F) / (eps_max - eps_min).
+void launch_gershgorin_scale(const double* f, int64_t n, int64_t ldf, double* row_lo,
+                             double* row_hi, double* row_max, Scale* scale, hipStream_t s);
+// max |F_ij - F_ji| into scale->max_asym.
+void launch_asymmetry(const double* f, int64_t n, int64_t ldf, Scale* scale, hipStream_t s);
+void launch_init_scale(Scale* scale, hipStream_t s);  // plain: diag 0, sign 1, div 1
+void launch_to_dense(const spamm_matrix* m, double* out, int64_t ld, hipStream_t s);
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+void launch_fill_f64(double* p, int64_t n, double v, hipStream_t s);
+
+// ---- scan.hip --------------------------------------------------------------
+
+// Exclusive scans of cnt[0..L) and of [cnt > 0], with L = mult * (*len_dev)
+// when len_dev is non-NULL (else len_host), optionally masked to zero when
+// *len_dev exceeds len_cap.  Totals go to *tot_cnt and *tot_nz; the sum of
+// err[0..L/mult) (fixed order) to *tot_err when err is non-NULL.
+struct ScanWork {
+  DevBuf part;
+};
+Error launch_scan(const int32_t* cnt, int64_t* off_cnt, int32_t* off_nz, const double* err,
+                 const int64_t* len_dev, int64_t len_cap, int mult, int64_t len_host,
+                 int64_t* tot_cnt, int64_t* tot_nz, double* tot_err, ScanWork& w,
+                 hipStream_t s);
+
+// ---- cull.hip --------------------------------------------------------------
+
+// Control block shared by the culling pass and the SP2 reductions, copied
+// to the host in one transfer per synchronisation.
+struct Control {
+  int64_t n_nodes[kMaxTiers];
+  int64_t n_tasks[kMaxTiers];
+  double err[kMaxTiers];
+  int64_t nonzero_pairs;
+  int64_t extra_blocks;   // SP2: blocks of X_n carried into X_{n+1} without products
+  double sp2_trace;       // tr X_{n+1}
+  double sp2_err2;        // ||C - X_n||_F^2
+  double frob2;           // ||X_{n+1}||_F^2
+  int64_t scratch[4];
+};
+
+struct CullWork {
+  int depth = -1;
+  int64_t cap_nodes[kMaxTiers] = {};
+  int64_t cap_tasks[kMaxTiers] = {};
+  DevBuf nodes[kMaxTiers], nptr[kMaxTiers], ks[kMaxTiers];
+  DevBuf cnt4, toff, noff, errp;
+  int64_t cap_count = 0;
+  ScanWork scan;
+  Control* ctl_dev = nullptr;
+  Control* ctl_host = nullptr;  // pinned
+  void release(hipStream_t s);
+  ~CullWork();
+};
+
+struct CullResult {
+  int64_t n_cblocks = 0, n_tasks = 0, nonzero_pairs = 0;
+  double err_bound = 0.0;
+  int restarts = 0;
+  const int32_t* nodes = nullptr;
+  const int64_t* nptr = nullptr;
+  const int32_t* ks = nullptr;
+};
+
+// Runs the occlusion pass tier by tier and synchronises `s` once (plus once
+// per regrowth of the frontier buffers).  With want_pairs the count of
+// non-zero block pairs is computed too.
+Error run_cull(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
+               bool want_pairs, hipStream_t s, CullResult* out);
+Error ensure_control(CullWork& w);
+
+// ---- leafgemm.hip ----------------------------------------------------------
+
+struct GemmArgs {
+  int nb;
+  int64_t n_nodes;
+  const int32_t* nodes;
+  const int64_t* nptr;
+  const int32_t* ks;
+  const void* pool_a;
+  const int32_t* map_a;
+  const void* pool_b;
+  const int32_t* map_b;
+  void* pool_c;
+  int32_t* map_c;
+  int32_t* coords_c;
+  double* norm_c;        // leaf tier of C's norms, [nb * nb]
+  // Fused SP2 update (sp2 != 0): X_{n+1} = C (square) or 2 X_n - C.
+  int sp2;
+  int square;
+  const void* pool_x;
+  const int32_t* map_x;
+  double* trace_part;    // [nb]
+  double* err_part;      // [nb * nb]
+};
+void launch_leaf_gemm(int prec, const GemmArgs& g, hipStream_t s);
+
+// SP2: blocks of X_n without any executed product.
+struct RestArgs {
+  int nb;
+  int square;
+  int64_t n_x;
+  const void* pool_x;
+  const int32_t* coords_x;
+  int64_t base_slot;     // first free slot of the output pool (= C blocks)
+  void* pool_out;
+  int32_t* map_out;
+  int32_t* coords_out;
+  double* norm_out;
+  double* trace_part;
+  double* err_part;
+  int64_t* counter;      // appended blocks
+};
+void launch_sp2_rest(int prec, const RestArgs& r, hipStream_t s);
+// Fixed-order sums of trace_part[nb], err_part[nb*nb] and the squared leaf
+// norms into ctl->sp2_trace, sp2_err2, frob2.
+void launch_sp2_reduce(int nb, const double* trace_part, const double* err_part,
+                       const double* norm_leaf, Control* ctl, hipStream_t s);
+
+}  // namespace spamm

@@ -1,0 +1,66 @@
+"""Host-side checks of the C ABI boundary (no device calls): the library
+loads and exports every function that include/spamm.h declares, and the
+binding's structure layouts match the header's."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "spamm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s+\**\s*([a-z_0-9]+)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for must in ("spamm_tree_build", "spamm_multiply", "sp2_solve", "spamm_cull",
+                 "spamm_to_dense", "spamm_matrix_destroy", "spamm_last_error"):
+        assert must in names
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    import paper_1403_7458_amd as sp
+    lib = sp.load()
+    out = subprocess.run(["nm", "-D", "--defined-only", sp.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    for name in declared_functions():
+        assert name in exported, name
+        assert hasattr(lib, name)
+    # The binding describes exactly the declared functions.
+    assert set(sp.SIGNATURES) == set(declared_functions())
+    assert sp.version().startswith("spamm-mi355x")
+
+
+def test_struct_sizes_match_the_header():
+    from paper_1403_7458_amd import _lib
+    # Sizes implied by the field lists of include/spamm.h (x86-64 System V).
+    assert ctypes.sizeof(_lib.SpammInfo) == 48
+    assert ctypes.sizeof(_lib.MultStats) == 48
+    assert ctypes.sizeof(_lib.Sp2Options) == 32
+    assert ctypes.sizeof(_lib.Sp2Stats) == 8 + 24 + 8 + 256 + 4 * 8 * 256
+    assert ctypes.sizeof(_lib.Profile) == 6 * 8 * 2 + 8
+
+
+def test_sp2_options_defaults_come_from_the_library():
+    from paper_1403_7458_amd import _lib
+    o = _lib.Sp2Options()
+    _lib.load().sp2_options_default(ctypes.byref(o))
+    assert (o.precision, o.max_iter, o.min_iter, o.stall_rule) == (1, 100, 0, 1)
+    assert o.tol == 1e-8 and o.stall_floor == 1e-3
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    from paper_1403_7458_amd import _lib
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(ImportError):
+        _lib.load(str(tmp_path / "libspamm.so"))
