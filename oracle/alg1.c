@@ -17,11 +17,11 @@
  *
  * Recursion (Alg. 1): on tier t < d, each of the eight child triples
  * (i', j', k') is tested with ||A^{t+1}_{i'k'}|| ||B^{t+1}_{k'j'}|| > tau
- * (reading Z2: the children's norms); a passing child is spawned as an
+ * (the children's norms, as Alg. 3 tests them); a passing child is spawned as an
  * untied task and the node waits for all of them.  On tier d the leaf
  * product C_ij += A_ik B_kj runs with three nested loops under the lock of
- * C_ij.  With depth 0 the single leaf is tested against tau first (reading
- * Z6); for depth >= 1 the root itself is not tested (Alg. 1 tests children
+ * C_ij.  With depth 0 the root is the single leaf and is tested against tau
+ * first; for depth >= 1 the root itself is not tested (Alg. 1 tests children
  * only), which changes nothing because norms are monotone up the tree.
  *
  * Also reported: the number of executed leaf products and the sum of

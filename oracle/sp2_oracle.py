@@ -8,19 +8,20 @@ Fockian, Sec. 4) by SP2 purification run to convergence, each iteration one
 SpAMM square, and cites Niklasson (2002) for the scheme without writing it
 out.  The steps below are that scheme as read for this build:
 
-1. Gershgorin bounds over the N active rows (reading Z10):
+1. Gershgorin bounds over the N active rows (the paper gives none):
    eps_min = min_i (F_ii - R_i), eps_max = max_i (F_ii + R_i),
    R_i = sum_{j != i} |F_ij|.
 2. X_0 = (eps_max I_N - F) / (eps_max - eps_min) on the active N x N block,
-   zero in the padding (readings Z7, Z9): low energies map towards 1, so the
+   zero in the padding (I_N, not the padded identity, so the padding adds
+   nothing to the trace): low energies map towards 1, so the
    projector is onto the n_occ lowest eigenvectors of F.
 3. For n = 0, 1, ...:
-     t_n = tr X_n;  C = SpAMM(X_n, X_n, tau);  e_n = ||C - X_n||_F  (Z13)
-     X_{n+1} = C if t_n > n_occ else 2 X_n - C                      (Z8)
+     t_n = tr X_n;  C = SpAMM(X_n, X_n, tau);  e_n = ||C - X_n||_F
+     X_{n+1} = C if t_n > n_occ else 2 X_n - C
      stop if e_n < tol (converged), or, with the stall rule on, if n >= 2,
      e_n < stall_floor and e_n >= e_{n-2} (stalled at the precision floor,
-     reading Z11), or when n + 1 = max_iter (not converged).
-   The returned projector is X_{n+1} of the stopping iteration (Z12).
+     the precision or culling floor), or when n + 1 = max_iter (not converged).
+   The returned projector is X_{n+1} of the stopping iteration.
    Stopping is only allowed once n + 1 >= min_iter.
 
 The SpAMM product is the flat definition (`spamm_oracle.spamm`) or the
@@ -53,7 +54,7 @@ class SP2Result:
 
 
 def gershgorin(f: np.ndarray) -> tuple[float, float]:
-    """Gershgorin bounds of the spectrum of symmetric F (reading Z10)."""
+    """Gershgorin bounds of the spectrum of symmetric F over its rows."""
     f = np.asarray(f, dtype=np.float64)
     d = np.diag(f)
     r = np.abs(f).sum(axis=1) - np.abs(d)
@@ -61,7 +62,7 @@ def gershgorin(f: np.ndarray) -> tuple[float, float]:
 
 
 def initial_x(f: np.ndarray, eps_min: float, eps_max: float, n_pad: int) -> np.ndarray:
-    """X_0 = (eps_max I_N - F) / (eps_max - eps_min), zero-padded (Z7, Z9)."""
+    """X_0 = (eps_max I_N - F) / (eps_max - eps_min), zero-padded."""
     n = f.shape[0]
     x = (eps_max * np.eye(n) - f) / (eps_max - eps_min)
     return pad(x, n_pad)

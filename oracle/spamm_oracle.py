@@ -28,10 +28,10 @@ definition; `executed_set_breadth_first` walks the tiers as Algs. 2-3 do
 and serves as a check of the equivalence; `oracle/alg1.c` is the recursive
 Alg. 1 form with tasks and per-block locks.
 
-Readings where the paper is silent (numbered as in the design notes):
-Z1 ties are culled (strict >); Z2 the test uses the children's norms;
-Z3/Z6 with depth 0 the single leaf product is itself tested against tau;
-Z5 tau is absolute, tau = 0 culls only exact-zero products, tau < 0 or NaN
+Readings where the paper is silent or garbled: ties are culled (strict >);
+the test uses the children's norms (Alg. 3; Alg. 1's superscripts are off by
+one tier); with depth 0 the single leaf product is itself tested against tau;
+tau is absolute, tau = 0 culls only exact-zero products, tau < 0 or NaN
 is rejected.
 """
 from __future__ import annotations
@@ -44,7 +44,7 @@ LEAF = 32
 
 
 def padded_size(n: int) -> int:
-    """N_pad = 32 * 2^d, the smallest such size >= n (Fig. 4 caption; Z6)."""
+    """N_pad = 32 * 2^d, the smallest such size >= n (Fig. 4 caption pads 2,250 to 4,096)."""
     if n < 1:
         raise ValueError("matrix dimension must be >= 1")
     nb = 1
@@ -159,7 +159,7 @@ def executed_set_breadth_first(tiers_a: list[np.ndarray], tiers_b: list[np.ndarr
     Tier 0 is enabled.  On every tier t < d each enabled triple (i, j, k)
     tests its eight children (2i+a, 2j+b, 2k+c) with the norms of tier t+1
     and enables those whose norm product exceeds tau.  With d = 0 the single
-    leaf is tested directly (reading Z6).
+    leaf is tested directly.
     """
     tau = check_tau(tau)
     d = len(tiers_a) - 1

@@ -205,7 +205,7 @@ def test_invalid_tau_rejected(tau):
 
 def test_depth_zero_leaf_is_tested():
     a = np.eye(4)                                # ||A|| = 2 exactly, product of norms 4
-    c, info = so.spamm(a, a, 4.0)                # tie: culled (strict >, reading Z1)
+    c, info = so.spamm(a, a, 4.0)                # tie: culled (strict > of Eq. 4)
     assert info["n_exec"] == 0 and not np.any(c)
     c2, i2 = alg1.spamm_alg1(a, a, 4.0)
     assert i2["n_exec"] == 0 and not np.any(c2)
