@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--molecules", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-multiply", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the SpAMM/SP2 path "
@@ -146,8 +148,11 @@ def main():
     achieved = LEAF_FLOP * per_launch / (gemm_ms * 1e-3) / 1e12
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": measured_traffic("leaf_gemm_f32", f"water{args.molecules}_tau{tau:g}"),
-                "kernel": "k_leaf_gemm_f32 (fused SP2 update)",
+                "traffic": measured_traffic(
+                    "leaf_gemm_f32_" + os.environ.get("SPAMM_LEAF_KERNEL", "w2x2s"),
+                    f"water{args.molecules}_tau{tau:g}"),
+                "kernel": "k_leaf_gemm_f32 " + os.environ.get("SPAMM_LEAF_KERNEL", "w2x2s")
+                          + " (fused SP2 update)",
                 "launches": launches, "mean_launch_ms": round(gemm_ms, 4),
                 "products_per_launch": round(per_launch, 1)}
     phase_ms = {k: round(v / args.steps, 3) for k, v in prof["ms"].items()}
@@ -182,6 +187,21 @@ def main():
         x0 = sp2o.initial_x(w.f, lo, hi, so.padded_size(n))
         cpu = cpu_baseline(x0, tau)
 
+    copy = None
+    if args.copy_mib > 0:
+        # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the per-dispatch HBM byte counts of the other kernels.
+        nbytes = args.copy_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        copy = {"bytes_read": nbytes, "bytes_written": nbytes,
+                "gbs": round(2 * nbytes / (time.perf_counter() - ts) / 1e9, 1)}
+        del src, dst
+
     line = {
         "metric": "SpAMM effective GFLOP/s & SP2 solves/sec at tau=1e-6; p50/p99 solve latency",
         "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
@@ -203,6 +223,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    if copy is not None:
+        line["copy_calibration"] = copy
     print(json.dumps(line), flush=True)
 
 

@@ -223,6 +223,22 @@ Error multiply_impl(const spamm_matrix* a, const spamm_matrix* b, double tau, hi
   g.nodes = cr.nodes;
   g.nptr = cr.nptr;
   g.ks = cr.ks;
+  g.n_super = cr.n_super;
+  g.sup_nodes = cr.sup_nodes;
+  g.sup_nptr = cr.sup_nptr;
+  g.sup_ks = cr.sup_ks;
+  g.sup_bits = cr.sup_bits;
+  g.sup_cnt4 = cr.sup_cnt4;
+  g.sup_noff = cr.sup_noff;
+  if (a->prec == SPAMM_FP32 && cr.n_quad > 0 && leaf_kernel_choice() == kLeaf4x4) {
+    launch_quad_masks(cr, a, b, tau, s);
+    launch_scatter_nodes(cr.nodes, cr.n_cblocks, c->nb, c->map, c->coords, s);
+    g.n_quad = cr.n_quad;
+    g.quad_nodes = cr.quad_nodes;
+    g.quad_nptr = cr.quad_nptr;
+    g.quad_ks = cr.quad_ks;
+    g.quad_masks = cr.quad_masks;
+  }
   g.pool_a = a->pool;
   g.map_a = a->map;
   g.pool_b = b->pool;
@@ -721,16 +737,30 @@ Error sp2_impl(const double* f, int64_t n, int64_t ldf, int64_t n_occ, double ta
       free_matrix(x);
       return e;
     }
-    launch_fill_i32(y->map, cells, -1, s);
-    launch_fill_f64(y->norms + tier_offset(y->depth), cells, 0.0, s);
-    launch_fill_f64(buf.trace_part, nb, 0.0, s);
-    launch_fill_f64(buf.err_part, cells, 0.0, s);
+    launch_sp2_prepare(y->map, y->norms + tier_offset(y->depth), buf.err_part, nb,
+                       buf.trace_part, &ctl->scratch[1], s);
     GemmArgs g{};
     g.nb = nb;
     g.n_nodes = cr.n_cblocks;
     g.nodes = cr.nodes;
     g.nptr = cr.nptr;
     g.ks = cr.ks;
+    g.n_super = cr.n_super;
+    g.sup_nodes = cr.sup_nodes;
+    g.sup_nptr = cr.sup_nptr;
+    g.sup_ks = cr.sup_ks;
+    g.sup_bits = cr.sup_bits;
+    g.sup_cnt4 = cr.sup_cnt4;
+    g.sup_noff = cr.sup_noff;
+    if (opt.precision == SPAMM_FP32 && cr.n_quad > 0 && leaf_kernel_choice() == kLeaf4x4) {
+      launch_quad_masks(cr, x, x, tau, s);
+      launch_scatter_nodes(cr.nodes, cr.n_cblocks, nb, y->map, y->coords, s);
+      g.n_quad = cr.n_quad;
+      g.quad_nodes = cr.quad_nodes;
+      g.quad_nptr = cr.quad_nptr;
+      g.quad_ks = cr.quad_ks;
+      g.quad_masks = cr.quad_masks;
+    }
     g.pool_a = x->pool;
     g.map_a = x->map;
     g.pool_b = x->pool;
@@ -751,7 +781,6 @@ Error sp2_impl(const double* f, int64_t n, int64_t ldf, int64_t n_occ, double ta
     }
     {
       PhaseTimer timer(SPAMM_PHASE_EPILOGUE, s);
-      launch_fill_i32(reinterpret_cast<int32_t*>(&ctl->scratch[1]), 2, 0, s);
       RestArgs r{};
       r.nb = nb;
       r.square = g.square;

@@ -11,8 +11,15 @@
 // come out ascending, so the leaf tier is the task list grouped by C block
 // with k ascending, in a fixed order, with no sort and no atomics.
 //
-// Frontier buffers have host-side capacities; kernels never write past
-// them.  When a tier's true size (computed on the device) exceeds its
+// Launches: the frontier of tier min(depth, 5) (at most 4^5 nodes, 8^5
+// triples, so its buffers are sized for the dense case) comes from one
+// single-workgroup launch.
+// Every deeper tier takes three launches over a fixed partition of its
+// parents into kParts chunks: count (+ chunk totals), scan of the chunk
+// totals, then in-chunk offsets + write.
+//
+// Deeper frontier buffers have host-side capacities; kernels never write
+// past them.  When a tier's true size (computed on the device) exceeds its
 // capacity, the pass is resumed from the tier above it with enough room.
 #include <algorithm>
 #include <cstring>
@@ -23,8 +30,10 @@ namespace spamm {
 
 namespace {
 
-constexpr int kWaves = 4;  // waves per workgroup
-constexpr int kMaxGrid = 4096;
+constexpr int kWaves = 4;      // waves per chunk workgroup
+constexpr int kParts = 1024;   // chunks per deep tier
+constexpr int kTopTier = 5;    // tier of the dense single-workgroup start
+constexpr int kTopThreads = 1024;
 
 struct TierIn {
   const int32_t* nodes;
@@ -33,40 +42,28 @@ struct TierIn {
   int64_t cap_nodes, cap_tasks;
 };
 
-__device__ inline int64_t parents_in(const Control* ctl, int t, int64_t cap_n, int64_t cap_t) {
-  const int64_t n = ctl->n_nodes[t], k = ctl->n_tasks[t];
-  return (n >= 0 && n <= cap_n && k >= 0 && k <= cap_t) ? n : 0;
+struct TierOut {
+  int32_t* nodes;
+  int64_t* nptr;
+  int32_t* ks;
+  int64_t cap_nodes, cap_tasks;
+};
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
 }
 
-__global__ void k_cull_init(Control* ctl, int depth, int32_t* nodes0, int64_t* nptr0, int32_t* ks0,
-                            const double* na_root, const double* nb_root, double tau) {
-  for (int t = 0; t < kMaxTiers; ++t) {
-    ctl->n_nodes[t] = -1;
-    ctl->n_tasks[t] = -1;
-    ctl->err[t] = 0.0;
+__device__ inline int64_t wave_incl_scan(int64_t v, int lane) {
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(v, o, 64);
+    if (lane >= o) v += y;
   }
-  ctl->nonzero_pairs = 0;
-  bool keep = true;
-  if (depth == 0) {
-    // A single leaf: the product itself is tested (the root is a leaf).
-    const double p = na_root[0] * nb_root[0];
-    keep = p > tau;
-    if (!keep) ctl->err[0] = p;
-  }
-  nptr0[0] = 0;
-  if (keep) {
-    nodes0[0] = pack_ij(0, 0);
-    ks0[0] = 0;
-    nptr0[1] = 1;
-    ctl->n_nodes[0] = 1;
-    ctl->n_tasks[0] = 1;
-  } else {
-    ctl->n_nodes[0] = 0;
-    ctl->n_tasks[0] = 0;
-  }
+  return v;
 }
 
 // Pass bits of the 8 children of (I, J, K): bit (q * 2 + c), q = 2a + b.
+// *culled gets the sum of the failing norm products.
 __device__ inline uint32_t child_bits(const double* __restrict__ na, const double* __restrict__ nb,
                                       int64_t w, int I, int J, int K, double tau, double* culled) {
   double av[2][2], bv[2][2];
@@ -96,101 +93,360 @@ __device__ inline uint32_t child_bits(const double* __restrict__ na, const doubl
   return bits;
 }
 
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// Counts of the 4 child C nodes of parent p (tasks per child) and the sum
+// of the culled products, for the wave that owns p.
+__device__ inline void count_parent(const TierIn& in, const double* na, const double* nb, int64_t w,
+                                    double tau, int64_t p, int lane, int32_t cq[4], double* err,
+                                    uint8_t* bits_out = nullptr) {
+  const int32_t ij = in.nodes[p];
+  const int I = unpack_i(ij), J = unpack_j(ij);
+  const int64_t beg = in.nptr[p], end = in.nptr[p + 1];
+  cq[0] = cq[1] = cq[2] = cq[3] = 0;
+  double e = 0.0;
+  for (int64_t x0 = beg; x0 < end; x0 += 64) {
+    const int64_t x = x0 + lane;
+    uint32_t bits = 0;
+    if (x < end) {
+      double ce;
+      bits = child_bits(na, nb, w, I, J, in.ks[x], tau, &ce);
+      e += ce;
+      if (bits_out) bits_out[x] = uint8_t(bits);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      cq[q] += __popcll(__ballot((bits >> (2 * q)) & 1)) +
+               __popcll(__ballot((bits >> (2 * q + 1)) & 1));
+  }
+  *err = wave_sum(e);
 }
 
-__global__ void __launch_bounds__(256) k_cull_count(TierIn in, const double* __restrict__ na,
-                                                    const double* __restrict__ nb, int t,
-                                                    double tau, Control* ctl,
-                                                    int32_t* __restrict__ cnt4,
-                                                    double* __restrict__ errp) {
-  const int64_t P = parents_in(ctl, t, in.cap_nodes, in.cap_tasks);
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->scratch[0] = P;
-  const int lane = threadIdx.x & 63;
-  const int64_t w = int64_t(2) << t;  // width of tier t+1
-  for (int64_t p = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6); p < P;
-       p += int64_t(gridDim.x) * kWaves) {
-    const int32_t ij = in.nodes[p];
-    const int I = unpack_i(ij), J = unpack_j(ij);
-    const int64_t beg = in.nptr[p], end = in.nptr[p + 1];
-    int32_t cq[4] = {0, 0, 0, 0};
-    double e = 0.0;
-    for (int64_t x0 = beg; x0 < end; x0 += 64) {
-      const int64_t x = x0 + lane;
-      uint32_t bits = 0;
-      if (x < end) {
-        double ce;
-        bits = child_bits(na, nb, w, I, J, in.ks[x], tau, &ce);
-        e += ce;
-      }
+// Writes the children of parent p: child node q (if non-empty) at index
+// noff[q] with its tasks from toff[q].
+__device__ inline void write_parent(const TierIn& in, const double* na, const double* nb, int64_t w,
+                                    double tau, int64_t p, int lane, const int32_t cq[4],
+                                    const int64_t toff[4], const int64_t noff[4],
+                                    const TierOut& out) {
+  const int32_t ij = in.nodes[p];
+  const int I = unpack_i(ij), J = unpack_j(ij);
+  const uint64_t below = (uint64_t(1) << lane) - 1;
+  int64_t pos[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-        cq[q] += __popcll(__ballot((bits >> (2 * q)) & 1)) +
-                 __popcll(__ballot((bits >> (2 * q + 1)) & 1));
+  for (int q = 0; q < 4; ++q) {
+    pos[q] = toff[q];
+    if (lane == 0 && cq[q] > 0) {
+      out.nodes[noff[q]] = pack_ij(2 * I + (q >> 1), 2 * J + (q & 1));
+      out.nptr[noff[q]] = toff[q];
     }
-    e = wave_sum(e);
-    if (lane == 0) {
+  }
+  const int64_t beg = in.nptr[p], end = in.nptr[p + 1];
+  for (int64_t x0 = beg; x0 < end; x0 += 64) {
+    const int64_t x = x0 + lane;
+    uint32_t bits = 0;
+    int K = 0;
+    if (x < end) {
+      double ce;
+      K = in.ks[x];
+      bits = child_bits(na, nb, w, I, J, K, tau, &ce);
+    }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) cnt4[4 * p + q] = cq[q];
-      errp[p] = e;
+    for (int q = 0; q < 4; ++q) {
+      const bool p0 = (bits >> (2 * q)) & 1, p1 = (bits >> (2 * q + 1)) & 1;
+      const uint64_t b0 = __ballot(p0), b1 = __ballot(p1);
+      const int64_t at = pos[q] + __popcll(b0 & below) + __popcll(b1 & below);
+      if (p0) out.ks[at] = 2 * K;
+      if (p1) out.ks[at + (p0 ? 1 : 0)] = 2 * K + 1;
+      pos[q] += __popcll(b0) + __popcll(b1);
     }
   }
 }
 
-__global__ void __launch_bounds__(256) k_cull_write(TierIn in, const double* __restrict__ na,
-                                                    const double* __restrict__ nb, int t,
-                                                    double tau, const Control* ctl,
-                                                    const int32_t* __restrict__ cnt4,
-                                                    const int64_t* __restrict__ toff,
-                                                    const int32_t* __restrict__ noff,
-                                                    int32_t* __restrict__ out_nodes,
-                                                    int64_t* __restrict__ out_nptr,
-                                                    int32_t* __restrict__ out_ks,
-                                                    int64_t cap_nodes_out,
-                                                    int64_t cap_tasks_out) {
-  const int64_t P = ctl->scratch[0];
-  const int64_t n_out = ctl->n_nodes[t + 1], k_out = ctl->n_tasks[t + 1];
-  if (n_out > cap_nodes_out || k_out > cap_tasks_out) return;  // resumed with more room
-  if (blockIdx.x == 0 && threadIdx.x == 0) out_nptr[n_out] = k_out;
-  const int lane = threadIdx.x & 63;
-  const uint64_t below = (uint64_t(1) << lane) - 1;
+// ---- top tiers: one workgroup ------------------------------------------------
+//
+// Tier t0 = min(depth, 5) is built directly from its own norms: by Eq. 3 a
+// node's norm bounds its descendants', so a tier-t0 triple passes every
+// ancestor test whenever it passes its own, and the frontier the walk would
+// reach at t0 is the flat set {(I, J, K) : ||A_IK|| ||B_KJ|| > tau} there
+// (up to rounding in the last bit of the norms, inside the tie band).
+// One thread per tier-t0 C node (Morton index), one bit per K.  The same
+// launch adds up the culled-product bound over the tiers 1..t0: a triple
+// counts when it fails and its parent passes (the root is never tested).
+
+struct TopArgs {
+  int depth, t0;
+  double tau;
+  const double* norms_a;
+  const double* norms_b;
+  int32_t* nodes;
+  int64_t* nptr;
+  int32_t* ks;
+  Control* ctl;
+};
+
+constexpr int kTopNorms = 1365;  // tiers 0..5: (4^6 - 1) / 3
+
+__device__ inline void demorton(int m, int bits, int* I, int* J) {
+  int i = 0, j = 0;
+  for (int b = 0; b < bits; ++b) {
+    j |= ((m >> (2 * b)) & 1) << b;
+    i |= ((m >> (2 * b + 1)) & 1) << b;
+  }
+  *I = i;
+  *J = j;
+}
+
+__global__ void __launch_bounds__(kTopThreads) k_cull_top(TopArgs g) {
+  __shared__ double sa[kTopNorms], sb[kTopNorms];
+  __shared__ int64_t s_wc[kTopThreads / 64], s_wz[kTopThreads / 64];
+  __shared__ double s_e[kTopThreads];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  Control* ctl = g.ctl;
+  const int t0 = g.t0;
+  if (tid < kMaxTiers) {
+    ctl->n_nodes[tid] = -1;
+    ctl->n_tasks[tid] = -1;
+    ctl->err[tid] = 0.0;
+  }
+  if (tid == 0) ctl->nonzero_pairs = 0;
+  const int n_norms = int(tier_offset(t0 + 1));
+  for (int x = tid; x < n_norms; x += kTopThreads) {
+    sa[x] = g.norms_a[x];
+    sb[x] = g.norms_b[x];
+  }
+  __syncthreads();
+  if (g.depth == 0) {
+    // A single leaf: the product itself is tested (the root is a leaf).
+    if (tid == 0) {
+      const double p = sa[0] * sb[0];
+      const bool keep = p > g.tau;
+      g.nptr[0] = 0;
+      if (keep) {
+        g.nodes[0] = pack_ij(0, 0);
+        g.ks[0] = 0;
+        g.nptr[1] = 1;
+      } else {
+        ctl->err[0] = p;
+      }
+      ctl->n_nodes[0] = keep ? 1 : 0;
+      ctl->n_tasks[0] = keep ? 1 : 0;
+    }
+    return;
+  }
+  const int W = 1 << t0;
+  const double* A = sa + tier_offset(t0);
+  const double* B = sb + tier_offset(t0);
+  int I = 0, J = 0;
+  uint32_t mask = 0;
+  if (tid < W * W) {
+    demorton(tid, t0, &I, &J);
+    for (int K = 0; K < W; ++K)
+      if (A[I * W + K] * B[K * W + J] > g.tau) mask |= 1u << K;
+  }
+  const int v = __popc(mask);
+  const int64_t ic = wave_incl_scan(v, lane), iz = wave_incl_scan(v > 0 ? 1 : 0, lane);
+  if (lane == 63) {
+    s_wc[wave] = ic;
+    s_wz[wave] = iz;
+  }
+  // Culled-product bound of tiers 1..t0, summed per thread in a fixed order.
+  double e = 0.0;
+  for (int t = 1; t <= t0; ++t) {
+    const int w = 1 << t;
+    const double* a = sa + tier_offset(t);
+    const double* b = sb + tier_offset(t);
+    const double* ap = sa + tier_offset(t - 1);
+    const double* bp = sb + tier_offset(t - 1);
+    for (int x = tid; x < w * w * w; x += kTopThreads) {
+      const int i = x >> (2 * t), j = (x >> t) & (w - 1), k = x & (w - 1);
+      const double p = a[i * w + k] * b[k * w + j];
+      if (p > g.tau) continue;
+      if (t > 1 && !(ap[(i / 2) * (w / 2) + k / 2] * bp[(k / 2) * (w / 2) + j / 2] > g.tau))
+        continue;
+      e += p;
+    }
+  }
+  s_e[tid] = e;
+  __syncthreads();
+  int64_t pc = 0, pz = 0, tc = 0, tz = 0;
+  for (int x = 0; x < kTopThreads / 64; ++x) {
+    if (x < wave) {
+      pc += s_wc[x];
+      pz += s_wz[x];
+    }
+    tc += s_wc[x];
+    tz += s_wz[x];
+  }
+  if (v > 0) {
+    const int64_t to = pc + ic - v, no = pz + iz - 1;
+    g.nodes[no] = pack_ij(I, J);
+    g.nptr[no] = to;
+    int r = 0;
+    for (uint32_t m = mask; m; m &= m - 1) g.ks[to + r++] = __ffs(m) - 1;
+  }
+  for (int o = kTopThreads / 2; o > 0; o >>= 1) {
+    if (tid < o) s_e[tid] += s_e[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    g.nptr[tz] = tc;
+    ctl->n_nodes[t0] = tz;
+    ctl->n_tasks[t0] = tc;
+    ctl->err[1] = s_e[0];
+  }
+}
+
+// ---- deep tiers: kParts chunks ---------------------------------------------
+
+__device__ inline int64_t parents_in(const Control* ctl, int t, int64_t cap_n, int64_t cap_t) {
+  const int64_t n = ctl->n_nodes[t], k = ctl->n_tasks[t];
+  return (n >= 0 && n <= cap_n && k >= 0 && k <= cap_t) ? n : 0;
+}
+
+// Per chunk: child counts into cnt4, and the chunk's totals (tasks,
+// non-empty children, culled-product sum) into part.
+__global__ void __launch_bounds__(64 * kWaves) k_cull_count(TierIn in, const double* __restrict__ na,
+                                                            const double* __restrict__ nb, int t,
+                                                            double tau, Control* ctl,
+                                                            int32_t* __restrict__ cnt4,
+                                                            int64_t* __restrict__ part,
+                                                            uint8_t* __restrict__ bits_out) {
+  __shared__ int64_t s_c[kWaves], s_z[kWaves];
+  __shared__ double s_e[kWaves];
+  const int64_t P = parents_in(ctl, t, in.cap_nodes, in.cap_tasks);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->scratch[0] = P;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t ch = (P + kParts - 1) / kParts;
+  const int64_t b0 = int64_t(blockIdx.x) * ch, b1 = min(P, b0 + ch);
   const int64_t w = int64_t(2) << t;
-  for (int64_t p = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6); p < P;
-       p += int64_t(gridDim.x) * kWaves) {
-    const int32_t ij = in.nodes[p];
-    const int I = unpack_i(ij), J = unpack_j(ij);
-    int64_t pos[4];
+  int64_t c = 0, z = 0;
+  double e = 0.0;
+  for (int64_t p = b0 + wave; p < b1; p += kWaves) {
+    int32_t cq[4];
+    double pe;
+    count_parent(in, na, nb, w, tau, p, lane, cq, &pe, bits_out);
+    e += pe;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      pos[q] = toff[4 * p + q];
-      if (lane == 0 && cnt4[4 * p + q] > 0) {
-        const int32_t c = noff[4 * p + q];
-        out_nodes[c] = pack_ij(2 * I + (q >> 1), 2 * J + (q & 1));
-        out_nptr[c] = pos[q];
-      }
+      c += cq[q];
+      z += cq[q] > 0;
     }
-    const int64_t beg = in.nptr[p], end = in.nptr[p + 1];
-    for (int64_t x0 = beg; x0 < end; x0 += 64) {
-      const int64_t x = x0 + lane;
-      uint32_t bits = 0;
-      int K = 0;
-      if (x < end) {
-        double ce;
-        K = in.ks[x];
-        bits = child_bits(na, nb, w, I, J, K, tau, &ce);
-      }
+    if (lane == 0) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const bool p0 = (bits >> (2 * q)) & 1, p1 = (bits >> (2 * q + 1)) & 1;
-        const uint64_t b0 = __ballot(p0), b1 = __ballot(p1);
-        const int64_t at = pos[q] + __popcll(b0 & below) + __popcll(b1 & below);
-        if (p0) out_ks[at] = 2 * K;
-        if (p1) out_ks[at + (p0 ? 1 : 0)] = 2 * K + 1;
-        pos[q] += __popcll(b0) + __popcll(b1);
-      }
+      for (int q = 0; q < 4; ++q) cnt4[4 * p + q] = cq[q];
     }
+  }
+  if (lane == 0) {
+    s_c[wave] = c;
+    s_z[wave] = z;
+    s_e[wave] = e;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t tc = 0, tz = 0;
+    double te = 0.0;
+    for (int x = 0; x < kWaves; ++x) {
+      tc += s_c[x];
+      tz += s_z[x];
+      te += s_e[x];
+    }
+    part[blockIdx.x] = tc;
+    part[kParts + blockIdx.x] = tz;
+    reinterpret_cast<double*>(part + 2 * kParts)[blockIdx.x] = te;
+  }
+}
+
+// Exclusive scan of the chunk totals; tier totals into the control block.
+__global__ void __launch_bounds__(kParts) k_cull_scan(int64_t* __restrict__ part, int t,
+                                                      Control* ctl) {
+  __shared__ int64_t s_wc[kParts / 64], s_wz[kParts / 64];
+  __shared__ double s_e[kParts];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t c = part[tid], z = part[kParts + tid];
+  s_e[tid] = reinterpret_cast<const double*>(part + 2 * kParts)[tid];
+  const int64_t ic = wave_incl_scan(c, lane), iz = wave_incl_scan(z, lane);
+  if (lane == 63) {
+    s_wc[wave] = ic;
+    s_wz[wave] = iz;
+  }
+  __syncthreads();
+  int64_t pc = 0, pz = 0, tc = 0, tz = 0;
+  for (int x = 0; x < kParts / 64; ++x) {
+    if (x < wave) {
+      pc += s_wc[x];
+      pz += s_wz[x];
+    }
+    tc += s_wc[x];
+    tz += s_wz[x];
+  }
+  part[tid] = pc + ic - c;
+  part[kParts + tid] = pz + iz - z;
+  for (int o = kParts / 2; o > 0; o >>= 1) {
+    if (tid < o) s_e[tid] += s_e[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    ctl->n_tasks[t + 1] = tc;
+    ctl->n_nodes[t + 1] = tz;
+    ctl->err[t + 1] = s_e[0];
+  }
+}
+
+// Per chunk: in-chunk exclusive offsets of the child counts, then the
+// children themselves.
+__global__ void __launch_bounds__(64 * kWaves) k_cull_write(TierIn in, const double* __restrict__ na,
+                                                            const double* __restrict__ nb, int t,
+                                                            double tau, const Control* ctl,
+                                                            const int32_t* __restrict__ cnt4,
+                                                            const int64_t* __restrict__ part,
+                                                            int64_t* __restrict__ toff,
+                                                            int64_t* __restrict__ noff,
+                                                            TierOut out) {
+  __shared__ int64_t s_wc[kWaves], s_wz[kWaves];
+  const int64_t P = ctl->scratch[0];
+  const int64_t n_out = ctl->n_nodes[t + 1], k_out = ctl->n_tasks[t + 1];
+  if (n_out > out.cap_nodes || k_out > out.cap_tasks) return;  // resumed with more room
+  if (blockIdx.x == 0 && threadIdx.x == 0) out.nptr[n_out] = k_out;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t ch = (P + kParts - 1) / kParts;
+  const int64_t b0 = int64_t(blockIdx.x) * ch, b1 = min(P, b0 + ch);
+  if (b0 >= b1) return;
+  int64_t base_c = part[blockIdx.x], base_z = part[kParts + blockIdx.x];
+  for (int64_t x0 = 4 * b0; x0 < 4 * b1; x0 += 64 * kWaves) {
+    const int64_t x = x0 + threadIdx.x;
+    const int32_t v = x < 4 * b1 ? cnt4[x] : 0;
+    const int64_t ic = wave_incl_scan(v, lane), iz = wave_incl_scan(v > 0 ? 1 : 0, lane);
+    if (lane == 63) {
+      s_wc[wave] = ic;
+      s_wz[wave] = iz;
+    }
+    __syncthreads();
+    int64_t pc = 0, pz = 0, tc = 0, tz = 0;
+    for (int y = 0; y < kWaves; ++y) {
+      if (y < wave) {
+        pc += s_wc[y];
+        pz += s_wz[y];
+      }
+      tc += s_wc[y];
+      tz += s_wz[y];
+    }
+    if (x < 4 * b1) {
+      toff[x] = base_c + pc + ic - v;
+      noff[x] = base_z + pz + iz - (v > 0 ? 1 : 0);
+    }
+    base_c += tc;
+    base_z += tz;
+    __syncthreads();
+  }
+  const int64_t w = int64_t(2) << t;
+  for (int64_t p = b0 + wave; p < b1; p += kWaves) {
+    int32_t cq[4];
+    int64_t to[4], no[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      cq[q] = cnt4[4 * p + q];
+      to[q] = toff[4 * p + q];
+      no[q] = noff[4 * p + q];
+    }
+    write_parent(in, na, nb, w, tau, p, lane, cq, to, no, out);
   }
 }
 
@@ -216,6 +472,52 @@ __global__ void __launch_bounds__(1024) k_nonzero_pairs(const double* __restrict
   if (threadIdx.x == 0) ctl->nonzero_pairs = sh[0];
 }
 
+// One wave per tier-(d-2) node, one lane per entry K: bit 16c + 4a + b is
+// set when leaf product (4I + a, 4J + b, 4K + c) passes and its tier-(d-1)
+// parent (2I + a/2, 2J + b/2, 2K + c/2) passes too, the same two tests, on
+// the same values, that the tier walk made for it.
+__global__ void __launch_bounds__(64 * kWaves) k_quad_masks(TierIn in, const double* __restrict__ na1,
+                                                            const double* __restrict__ nb1,
+                                                            const double* __restrict__ na,
+                                                            const double* __restrict__ nb, int d,
+                                                            double tau, int64_t P,
+                                                            uint64_t* __restrict__ masks) {
+  const int lane = threadIdx.x & 63;
+  const int64_t w1 = int64_t(1) << (d - 1), w = int64_t(1) << d;
+  for (int64_t p = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6); p < P;
+       p += int64_t(gridDim.x) * kWaves) {
+    const int32_t ij = in.nodes[p];
+    const int I = unpack_i(ij), J = unpack_j(ij);
+    const int64_t beg = in.nptr[p], end = in.nptr[p + 1];
+    for (int64_t x = beg + lane; x < end; x += 64) {
+      const int K = in.ks[x];
+      uint64_t m = 0;
+      for (int c = 0; c < 4; ++c) {
+        const int k = 4 * K + c, k1 = 2 * K + c / 2;
+        for (int a = 0; a < 4; ++a) {
+          const double pa1 = na1[int64_t(2 * I + a / 2) * w1 + k1];
+          const double pa = na[int64_t(4 * I + a) * w + k];
+          for (int b = 0; b < 4; ++b) {
+            const bool parent = pa1 * nb1[int64_t(k1) * w1 + 2 * J + b / 2] > tau;
+            const bool leaf = pa * nb[int64_t(k) * w + 4 * J + b] > tau;
+            if (parent && leaf) m |= uint64_t(1) << (16 * c + 4 * a + b);
+          }
+        }
+      }
+      masks[x] = m;
+    }
+  }
+}
+
+__global__ void k_scatter_nodes(const int32_t* __restrict__ nodes, int64_t n, int nb,
+                                int32_t* __restrict__ map_c, int32_t* __restrict__ coords_c) {
+  const int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (x >= n) return;
+  const int32_t ij = nodes[x];
+  map_c[int64_t(unpack_i(ij)) * nb + unpack_j(ij)] = int32_t(x);
+  coords_c[x] = ij;
+}
+
 inline int64_t pow_cap(int base_log2, int t, int64_t cap) {
   const int sh = base_log2 * t;
   if (sh >= 62) return cap;
@@ -226,38 +528,62 @@ Error reserve_tier(CullWork& w, int t, hipStream_t s) {
   SPAMM_TRY(w.nodes[t].reserve(size_t(std::max<int64_t>(w.cap_nodes[t], 1)) * 4, s));
   SPAMM_TRY(w.nptr[t].reserve(size_t(w.cap_nodes[t] + 1) * 8, s));
   SPAMM_TRY(w.ks[t].reserve(size_t(std::max<int64_t>(w.cap_tasks[t], 1)) * 4, s));
+  if (t + 1 == w.depth)
+    SPAMM_TRY(w.bits.reserve(size_t(std::max<int64_t>(w.cap_tasks[t], 1)), s));
+  if (t + 2 == w.depth)
+    SPAMM_TRY(w.quad.reserve(size_t(std::max<int64_t>(w.cap_tasks[t], 1)) * 8, s));
   const int64_t need = 4 * std::max<int64_t>(w.cap_nodes[t], 1);
   if (need > w.cap_count) {
     SPAMM_TRY(w.cnt4.reserve(size_t(need) * 4, s));
     SPAMM_TRY(w.toff.reserve(size_t(need) * 8, s));
-    SPAMM_TRY(w.noff.reserve(size_t(need) * 4, s));
-    SPAMM_TRY(w.errp.reserve(size_t(need / 4) * 8, s));
+    SPAMM_TRY(w.noff.reserve(size_t(need) * 8, s));
     w.cap_count = need;
   }
   return Error{};
 }
 
-Error expand(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, int t, double tau,
-             hipStream_t s) {
-  TierIn in{static_cast<const int32_t*>(w.nodes[t].p), static_cast<const int64_t*>(w.nptr[t].p),
-            static_cast<const int32_t*>(w.ks[t].p), w.cap_nodes[t], w.cap_tasks[t]};
+TierIn tier_in(CullWork& w, int t) {
+  return TierIn{static_cast<const int32_t*>(w.nodes[t].p), static_cast<const int64_t*>(w.nptr[t].p),
+                static_cast<const int32_t*>(w.ks[t].p), w.cap_nodes[t], w.cap_tasks[t]};
+}
+
+TierOut tier_out(CullWork& w, int t) {
+  return TierOut{static_cast<int32_t*>(w.nodes[t].p), static_cast<int64_t*>(w.nptr[t].p),
+                 static_cast<int32_t*>(w.ks[t].p), w.cap_nodes[t], w.cap_tasks[t]};
+}
+
+void expand(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, int t, double tau,
+            hipStream_t s) {
+  const TierIn in = tier_in(w, t);
   const double* na = a->norms + tier_offset(t + 1);
   const double* nb = b->norms + tier_offset(t + 1);
-  const unsigned grid =
-      unsigned(std::min<int64_t>((w.cap_nodes[t] + kWaves - 1) / kWaves, kMaxGrid));
+  int64_t* part = static_cast<int64_t*>(w.part.p);
   Control* ctl = w.ctl_dev;
-  k_cull_count<<<grid, 256, 0, s>>>(in, na, nb, t, tau, ctl, static_cast<int32_t*>(w.cnt4.p),
-                                    static_cast<double*>(w.errp.p));
-  SPAMM_TRY(launch_scan(static_cast<const int32_t*>(w.cnt4.p), static_cast<int64_t*>(w.toff.p),
-                        static_cast<int32_t*>(w.noff.p), static_cast<const double*>(w.errp.p),
-                        &ctl->scratch[0], w.cap_nodes[t], 4, 0, &ctl->n_tasks[t + 1],
-                        &ctl->n_nodes[t + 1], &ctl->err[t + 1], w.scan, s));
-  k_cull_write<<<grid, 256, 0, s>>>(
-      in, na, nb, t, tau, ctl, static_cast<const int32_t*>(w.cnt4.p),
-      static_cast<const int64_t*>(w.toff.p), static_cast<const int32_t*>(w.noff.p),
-      static_cast<int32_t*>(w.nodes[t + 1].p), static_cast<int64_t*>(w.nptr[t + 1].p),
-      static_cast<int32_t*>(w.ks[t + 1].p), w.cap_nodes[t + 1], w.cap_tasks[t + 1]);
-  return Error{};
+  // The last expansion also keeps each tier-(d-1) triple's 8 pass bits for
+  // the leaf products' 2 x 2 block groups.
+  uint8_t* bits = t + 1 == a->depth ? static_cast<uint8_t*>(w.bits.p) : nullptr;
+  k_cull_count<<<kParts, 64 * kWaves, 0, s>>>(in, na, nb, t, tau, ctl,
+                                              static_cast<int32_t*>(w.cnt4.p), part, bits);
+  k_cull_scan<<<1, kParts, 0, s>>>(part, t, ctl);
+  k_cull_write<<<kParts, 64 * kWaves, 0, s>>>(in, na, nb, t, tau, ctl,
+                                              static_cast<const int32_t*>(w.cnt4.p), part,
+                                              static_cast<int64_t*>(w.toff.p),
+                                              static_cast<int64_t*>(w.noff.p), tier_out(w, t + 1));
+}
+
+void launch_top(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, int t0, double tau,
+                hipStream_t s) {
+  TopArgs g{};
+  g.depth = a->depth;
+  g.t0 = t0;
+  g.tau = tau;
+  g.norms_a = a->norms;
+  g.norms_b = b->norms;
+  g.nodes = static_cast<int32_t*>(w.nodes[t0].p);
+  g.nptr = static_cast<int64_t*>(w.nptr[t0].p);
+  g.ks = static_cast<int32_t*>(w.ks[t0].p);
+  g.ctl = w.ctl_dev;
+  k_cull_top<<<1, kTopThreads, 0, s>>>(g);
 }
 
 }  // namespace
@@ -276,10 +602,11 @@ void CullWork::release(hipStream_t s) {
     ks[t].release(s);
   }
   cnt4.release(s);
+  bits.release(s);
+  quad.release(s);
   toff.release(s);
   noff.release(s);
-  errp.release(s);
-  scan.part.release(s);
+  part.release(s);
   cap_count = 0;
   depth = -1;
 }
@@ -294,24 +621,30 @@ CullWork::~CullWork() {
 Error run_cull(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
                bool want_pairs, hipStream_t s, CullResult* out) {
   const int d = a->depth;
+  const int t_top = std::min(d, kTopTier);
   SPAMM_TRY(ensure_control(w));
   if (w.depth != d) {
-    // First use at this depth: modest capacities, regrown on demand.
+    // Top tiers: the dense bound (4^t nodes, 8^t triples).  Deeper tiers:
+    // modest capacities, regrown on demand.
     for (int t = 0; t <= d; ++t) {
-      w.cap_nodes[t] = std::max<int64_t>(1, pow_cap(2, t, int64_t(1) << 16));
-      w.cap_tasks[t] = std::max<int64_t>(1, pow_cap(3, t, int64_t(1) << 18));
+      if (t <= t_top) {
+        w.cap_nodes[t] = pow_cap(2, t, int64_t(1) << 62);
+        w.cap_tasks[t] = pow_cap(3, t, int64_t(1) << 62);
+      } else {
+        w.cap_nodes[t] = std::max<int64_t>(1, pow_cap(2, t, int64_t(1) << 16));
+        w.cap_tasks[t] = std::max<int64_t>(1, pow_cap(3, t, int64_t(1) << 18));
+      }
     }
     w.depth = d;
   }
   for (int t = 0; t <= d; ++t) SPAMM_TRY(reserve_tier(w, t, s));
+  SPAMM_TRY(w.part.reserve(3 * kParts * sizeof(int64_t), s));
   Control* ctl = w.ctl_dev;
   out->restarts = 0;
   {
     PhaseTimer timer(SPAMM_PHASE_CULL, s);
-    k_cull_init<<<1, 1, 0, s>>>(ctl, d, static_cast<int32_t*>(w.nodes[0].p),
-                                static_cast<int64_t*>(w.nptr[0].p), static_cast<int32_t*>(w.ks[0].p),
-                                a->norms, b->norms, tau);
-    for (int t = 0; t < d; ++t) SPAMM_TRY(expand(w, a, b, t, tau, s));
+    launch_top(w, a, b, t_top, tau, s);
+    for (int t = t_top; t < d; ++t) expand(w, a, b, t, tau, s);
     if (want_pairs)
       k_nonzero_pairs<<<1, 1024, 0, s>>>(a->norms + tier_offset(d), b->norms + tier_offset(d),
                                          a->nb, ctl);
@@ -338,10 +671,10 @@ Error run_cull(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double
       w.cap_nodes[bad + 1] = std::max(w.cap_nodes[bad + 1], cn);
       w.cap_tasks[bad + 1] = std::max(w.cap_tasks[bad + 1], ct);
     }
-    for (int t = bad; t <= std::min(d, bad + 1); ++t) SPAMM_TRY(reserve_tier(w, t, s));
+    for (int t = bad - 1; t <= std::min(d, bad + 1); ++t) SPAMM_TRY(reserve_tier(w, t, s));
     ++out->restarts;
     PhaseTimer timer(SPAMM_PHASE_CULL, s);
-    for (int t = bad - 1; t < d; ++t) SPAMM_TRY(expand(w, a, b, t, tau, s));
+    for (int t = bad - 1; t < d; ++t) expand(w, a, b, t, tau, s);
   }
   const Control& h = *w.ctl_host;
   out->n_cblocks = h.n_nodes[d];
@@ -353,7 +686,41 @@ Error run_cull(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double
   out->nodes = static_cast<const int32_t*>(w.nodes[d].p);
   out->nptr = static_cast<const int64_t*>(w.nptr[d].p);
   out->ks = static_cast<const int32_t*>(w.ks[d].p);
+  if (d >= 1) {
+    out->n_super = h.n_nodes[d - 1];
+    out->sup_nodes = static_cast<const int32_t*>(w.nodes[d - 1].p);
+    out->sup_nptr = static_cast<const int64_t*>(w.nptr[d - 1].p);
+    out->sup_ks = static_cast<const int32_t*>(w.ks[d - 1].p);
+    out->sup_bits = static_cast<const uint8_t*>(w.bits.p);
+    out->sup_cnt4 = static_cast<const int32_t*>(w.cnt4.p);
+    out->sup_noff = static_cast<const int64_t*>(w.noff.p);
+  }
+  if (d >= 2) {
+    out->n_quad = h.n_nodes[d - 2];
+    out->quad_nodes = static_cast<const int32_t*>(w.nodes[d - 2].p);
+    out->quad_nptr = static_cast<const int64_t*>(w.nptr[d - 2].p);
+    out->quad_ks = static_cast<const int32_t*>(w.ks[d - 2].p);
+    out->quad_masks = static_cast<uint64_t*>(w.quad.p);
+  }
   return Error{};
+}
+
+void launch_quad_masks(const CullResult& r, const spamm_matrix* a, const spamm_matrix* b,
+                       double tau, hipStream_t s) {
+  if (r.n_quad <= 0) return;
+  const int d = a->depth;
+  TierIn in{r.quad_nodes, r.quad_nptr, r.quad_ks, 0, 0};
+  const unsigned grid = unsigned(std::min<int64_t>((r.n_quad + kWaves - 1) / kWaves, 8192));
+  k_quad_masks<<<grid, 64 * kWaves, 0, s>>>(in, a->norms + tier_offset(d - 1),
+                                            b->norms + tier_offset(d - 1), a->norms + tier_offset(d),
+                                            b->norms + tier_offset(d), d, tau, r.n_quad,
+                                            r.quad_masks);
+}
+
+void launch_scatter_nodes(const int32_t* nodes, int64_t n, int nb, int32_t* map_c,
+                          int32_t* coords_c, hipStream_t s) {
+  if (n <= 0) return;
+  k_scatter_nodes<<<unsigned((n + 255) / 256), 256, 0, s>>>(nodes, n, nb, map_c, coords_c);
 }
 
 }  // namespace spamm

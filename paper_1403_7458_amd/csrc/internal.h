@@ -174,9 +174,8 @@ struct CullWork {
   int64_t cap_nodes[kMaxTiers] = {};
   int64_t cap_tasks[kMaxTiers] = {};
   DevBuf nodes[kMaxTiers], nptr[kMaxTiers], ks[kMaxTiers];
-  DevBuf cnt4, toff, noff, errp;
+  DevBuf cnt4, toff, noff, part, bits, quad;
   int64_t cap_count = 0;
-  ScanWork scan;
   Control* ctl_dev = nullptr;
   Control* ctl_host = nullptr;  // pinned
   void release(hipStream_t s);
@@ -190,6 +189,26 @@ struct CullResult {
   const int32_t* nodes = nullptr;
   const int64_t* nptr = nullptr;
   const int32_t* ks = nullptr;
+  // Tier d-1 (depth >= 1): the 2 x 2 groups of C blocks, each with its
+  // ascending K list, the 8 pass bits of every entry (bit 2q + c for child
+  // C block q = 2a + b and leaf k = 2K + c), and per child q its leaf task
+  // count and C-block index (cnt4[4p + q], noff[4p + q]).
+  int64_t n_super = 0;
+  const int32_t* sup_nodes = nullptr;
+  const int64_t* sup_nptr = nullptr;
+  const int32_t* sup_ks = nullptr;
+  const uint8_t* sup_bits = nullptr;
+  const int32_t* sup_cnt4 = nullptr;
+  const int64_t* sup_noff = nullptr;
+  // Tier d-2 (depth >= 2): the 4 x 4 groups of C blocks with their K lists
+  // and, per entry, the 64 pass bits of its leaf products (bit 16c + 4a + b
+  // for C block (4I + a, 4J + b) and leaf k = 4K + c), filled by
+  // launch_quad_masks.
+  int64_t n_quad = 0;
+  const int32_t* quad_nodes = nullptr;
+  const int64_t* quad_nptr = nullptr;
+  const int32_t* quad_ks = nullptr;
+  uint64_t* quad_masks = nullptr;
 };
 
 // Runs the occlusion pass tier by tier and synchronises `s` once (plus once
@@ -198,6 +217,14 @@ struct CullResult {
 Error run_cull(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
                bool want_pairs, hipStream_t s, CullResult* out);
 Error ensure_control(CullWork& w);
+// The 64-bit leaf masks of the tier d-2 frontier (see CullResult).  Each bit
+// repeats the decisions the tier walk took for that leaf product and its
+// tier d-1 parent.
+void launch_quad_masks(const CullResult& r, const spamm_matrix* a, const spamm_matrix* b,
+                       double tau, hipStream_t s);
+// map_c[i * nb + j] = x and coords_c[x] = (i, j) for the C blocks of a task list.
+void launch_scatter_nodes(const int32_t* nodes, int64_t n, int nb, int32_t* map_c,
+                          int32_t* coords_c, hipStream_t s);
 
 // ---- leafgemm.hip ----------------------------------------------------------
 
@@ -207,6 +234,22 @@ struct GemmArgs {
   const int32_t* nodes;
   const int64_t* nptr;
   const int32_t* ks;
+  // 2 x 2 block groups of tier d-1 (see CullResult); n_super = 0 selects
+  // one wave per C block over the leaf task list instead.
+  int64_t n_super;
+  const int32_t* sup_nodes;
+  const int64_t* sup_nptr;
+  const int32_t* sup_ks;
+  const uint8_t* sup_bits;
+  const int32_t* sup_cnt4;
+  const int64_t* sup_noff;
+  // 4 x 4 block groups of tier d-2 (see CullResult); used when n_quad > 0.
+  // map_c must then already hold the C blocks (launch_scatter_nodes).
+  int64_t n_quad;
+  const int32_t* quad_nodes;
+  const int64_t* quad_nptr;
+  const int32_t* quad_ks;
+  const uint64_t* quad_masks;
   const void* pool_a;
   const int32_t* map_a;
   const void* pool_b;
@@ -223,6 +266,16 @@ struct GemmArgs {
   double* trace_part;    // [nb]
   double* err_part;      // [nb * nb]
 };
+// Leaf-product kernels (all add the same products in the same order):
+//   block  one wave per C block;
+//   2x2    4 waves per 2 x 2 group of C blocks, operands staged in LDS;
+//   4x4    4 waves per 4 x 4 group, operands staged in LDS;
+//   w2x2   one wave per 2 x 2 group, operands in registers, next step's
+//          loads in flight; w2x2s the same with one operand set (default:
+//          fastest measured on the 150-molecule workload).
+enum { kLeafBlock = 0, kLeaf2x2 = 1, kLeaf4x4 = 2, kLeafW2x2 = 3, kLeafW2x2s = 4,
+       kLeafDefault = kLeafW2x2s };
+int leaf_kernel_choice();
 void launch_leaf_gemm(int prec, const GemmArgs& g, hipStream_t s);
 
 // SP2: blocks of X_n without any executed product.
@@ -242,6 +295,10 @@ struct RestArgs {
   int64_t* counter;      // appended blocks
 };
 void launch_sp2_rest(int prec, const RestArgs& r, hipStream_t s);
+// map(-1), leaf norms, err_part (nb*nb), trace_part (nb) and the counter
+// cleared for one SP2 iteration.
+void launch_sp2_prepare(int32_t* map, double* norm_leaf, double* err_part, int nb,
+                        double* trace_part, int64_t* counter, hipStream_t s);
 // Fixed-order sums of trace_part[nb], err_part[nb*nb] and the squared leaf
 // norms into ctl->sp2_trace, sp2_err2, frob2.
 void launch_sp2_reduce(int nb, const double* trace_part, const double* err_part,

@@ -18,6 +18,10 @@
 //   FP64: v_mfma_f64_16x16x4f64 on the 2 x 2 sub-blocks, 8 steps each.
 //         A lane l: row l%16, k = (l/16)*8 + s; B lane l: col l%16.
 //         D reg r: row l/16 + 4r, col l%16.
+#include <algorithm>
+#include <cstdlib>
+#include <cstring>
+
 #include "internal.h"
 
 namespace spamm {
@@ -29,6 +33,26 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 4;
+constexpr int kXcds = 8;
+
+// Workgroups are dispatched to the 8 XCDs round-robin; renumber them so
+// that each XCD (and its L2) works through one contiguous range of the
+// Morton-ordered C blocks, whose A rows and B columns overlap.
+__device__ inline int64_t xcd_contiguous_block() {
+  const int64_t g = gridDim.x, b = blockIdx.x;
+  const int64_t x = b % kXcds, r = b / kXcds;
+  const int64_t q = g / kXcds, rem = g % kXcds;
+  return x * q + min(x, rem) + r;
+}
+
+// Wave-uniform copies (scalar registers), so that loops over a C block's
+// tasks compile to scalar branches with exact memory waits.
+__device__ inline int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline int64_t uniform(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+  return int64_t((uint64_t(hi) << 32) | lo);
+}
 
 __device__ inline double wave_sum(double v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -70,6 +94,47 @@ struct Epi {
   }
 };
 
+// Tile slots of a C block's tasks, looked up 64 at a time (one task per
+// lane) into a per-wave LDS list.  Reading a slot is then an LDS load, so
+// the operand loads of the next product never wait behind the index loads
+// (k, then the two block maps) or behind the current product's operands.
+struct TaskSlots {
+  const GemmArgs& g;
+  int i, j;
+  int64_t t1, base;
+  int32_t* lds;  // [2][64] for this wave
+  __device__ TaskSlots(const GemmArgs& g_, int i_, int j_, int64_t t0, int64_t t1_, int32_t* lds_,
+                       int lane)
+      : g(g_), i(i_), j(j_), t1(t1_), lds(lds_) {
+    fetch(t0, lane);
+  }
+  __device__ inline void fetch(int64_t b, int lane) {
+    base = b;
+    const int64_t t = b + lane;
+    int32_t sa = 0, sb = 0;
+    if (t < t1) {
+      const int k = g.ks[t];
+      sa = g.map_a[int64_t(i) * g.nb + k];
+      sb = g.map_b[int64_t(k) * g.nb + j];
+    }
+    lds[lane] = sa;
+    lds[64 + lane] = sb;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+  // Call before a(t) / b(t) when t may have left the current batch.
+  __device__ inline void advance(int64_t t, int lane) {
+    if (t - base >= 64) fetch(t, lane);
+  }
+  __device__ inline int64_t a(int64_t t) const {
+    return __builtin_amdgcn_readfirstlane(lds[t - base]);
+  }
+  __device__ inline int64_t b(int64_t t) const {
+    return __builtin_amdgcn_readfirstlane(lds[64 + (t - base)]);
+  }
+};
+
 struct F32Frag {
   v4f a[4];
   float b[16];
@@ -94,26 +159,44 @@ __device__ inline void mma_f32(const F32Frag& f, v16f& acc) {
 
 __global__ void __launch_bounds__(256) k_leaf_gemm_f32(GemmArgs g) {
   const int lane = threadIdx.x & 63;
-  const int64_t node = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+  const int64_t node = uniform(xcd_contiguous_block() * kWaves + (threadIdx.x >> 6));
   if (node >= g.n_nodes) return;
-  const int32_t ij = g.nodes[node];
+  const int32_t ij = uniform(g.nodes[node]);
   const int i = unpack_i(ij), j = unpack_j(ij);
   const float* pa = static_cast<const float*>(g.pool_a);
   const float* pb = static_cast<const float*>(g.pool_b);
-  const int64_t t0 = g.nptr[node], t1 = g.nptr[node + 1];
+  const int64_t t0 = uniform(g.nptr[node]), t1 = uniform(g.nptr[node + 1]);
   v16f acc = {};
   F32Frag cur, nxt;
-  auto tile_a = [&](int64_t t) {
-    return pa + int64_t(g.map_a[int64_t(i) * g.nb + g.ks[t]]) * kLeaf2;
-  };
-  auto tile_b = [&](int64_t t) {
-    return pb + int64_t(g.map_b[int64_t(g.ks[t]) * g.nb + j]) * kLeaf2;
-  };
-  if (t0 < t1) load_f32(tile_a(t0), tile_b(t0), lane, cur);
-  for (int64_t t = t0; t < t1; ++t) {
-    if (t + 1 < t1) load_f32(tile_a(t + 1), tile_b(t + 1), lane, nxt);
-    mma_f32(cur, acc);
-    cur = nxt;
+  __shared__ int32_t s_slots[kWaves][128];
+  TaskSlots ts(g, i, j, t0, t1, s_slots[threadIdx.x >> 6], lane);
+  if (t0 < t1) {
+    // Two operand sets in alternation: the next product's loads are always
+    // in flight while the current product runs on the MFMA unit.  The loop
+    // body has no conditional loads, so the waits stay exact.
+    auto fetch = [&](int64_t t, F32Frag& f) {
+      ts.advance(t, lane);
+      load_f32(pa + ts.a(t) * kLeaf2, pb + ts.b(t) * kLeaf2, lane, f);
+    };
+    fetch(t0, cur);
+    int64_t t = t0;
+    for (; t + 2 < t1; t += 2) {
+      fetch(t + 1, nxt);
+      __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
+      mma_f32(cur, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(t + 2, cur);
+      __builtin_amdgcn_sched_barrier(0);
+      mma_f32(nxt, acc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (t + 1 < t1) {
+      fetch(t + 1, nxt);
+      mma_f32(cur, acc);
+      mma_f32(nxt, acc);
+    } else {
+      mma_f32(cur, acc);
+    }
   }
   float* out = static_cast<float*>(g.pool_c) + node * kLeaf2;
   const float* xt = nullptr;
@@ -130,6 +213,456 @@ __global__ void __launch_bounds__(256) k_leaf_gemm_f32(GemmArgs g) {
     out[row * kLeaf + col] = e.apply(acc[r], x, g.sp2, g.square, i == j && row == col);
   }
   e.finish(g, node, ij, lane);
+}
+
+// ---- FP32 leaf products on 2 x 2 groups of C blocks --------------------------
+//
+// One workgroup of 4 waves owns the 2 x 2 C blocks (2I + a, 2J + b) below a
+// tier-(d-1) node (I, J); wave q = 2a + b owns block q.  Its work is the
+// node's ascending K list from the occlusion pass, each entry carrying the
+// 8 pass bits of (q, leaf k = 2K + c).  For every leaf k in ascending
+// order, the tiles A_{2I+a,k} and B_{k,2J+b} that some owner needs are
+// loaded once into LDS (double-buffered; the next k's tiles travel through
+// registers while the current k's products run) and each owner whose bit is
+// set runs its 16 MFMAs from there, so an A or B tile read from memory feeds
+// up to two products.  The accumulation order of every C block is its
+// ascending k, exactly as with one wave per block.
+
+constexpr int kBatch = 64;             // list entries staged per batch
+constexpr int kSteps = 2 * kBatch;     // leaf steps per batch (c = 0, 1)
+constexpr int kAStride = kLeaf + 4;    // padded A rows: conflict-free b128 reads
+
+struct StepTable {
+  int32_t mask[kSteps];     // bit q: owner q multiplies at this step
+  int32_t slot[kSteps][4];  // A_{2I}, A_{2I+1}, B_{,2J}, B_{,2J+1}; -1 if unused
+};
+
+__global__ void __launch_bounds__(256) k_leaf_gemm_f32_2x2(GemmArgs g) {
+  __shared__ float s_a[2][2][kLeaf * kAStride];
+  __shared__ float s_b[2][2][kLeaf2];
+  __shared__ StepTable st;
+  __shared__ int32_t s_wcnt[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t p = uniform(xcd_contiguous_block());
+  if (p >= g.n_super) return;
+  const int32_t IJ = uniform(g.sup_nodes[p]);
+  const int I = unpack_i(IJ), J = unpack_j(IJ);
+  const int a_own = wave >> 1, b_own = wave & 1;
+  const float* pa = static_cast<const float*>(g.pool_a);
+  const float* pb = static_cast<const float*>(g.pool_b);
+  const int64_t e0 = uniform(g.sup_nptr[p]), e1 = uniform(g.sup_nptr[p + 1]);
+  // Tile element of this thread while staging: row tid / 8, columns 4 (tid % 8) ..
+  const int srow = tid >> 3, scol = (tid & 7) * 4;
+  v16f acc = {};
+  v4f r0[4], r1[4];
+  for (int64_t eb = e0; eb < e1; eb += kBatch) {
+    // Step table of this batch: thread x < kSteps takes entry x / 2, c = x % 2.
+    int32_t mask = 0, sl[4] = {-1, -1, -1, -1};
+    if (tid < kSteps) {
+      const int64_t e = eb + (tid >> 1);
+      if (e < e1) {
+        const int c = tid & 1;
+        const int bits = g.sup_bits[e];
+        for (int q = 0; q < 4; ++q) mask |= ((bits >> (2 * q + c)) & 1) << q;
+        const int k = 2 * g.sup_ks[e] + c;
+        if (mask & 0x3) sl[0] = g.map_a[int64_t(2 * I) * g.nb + k];
+        if (mask & 0xC) sl[1] = g.map_a[int64_t(2 * I + 1) * g.nb + k];
+        if (mask & 0x5) sl[2] = g.map_b[int64_t(k) * g.nb + 2 * J];
+        if (mask & 0xA) sl[3] = g.map_b[int64_t(k) * g.nb + 2 * J + 1];
+      }
+    }
+    // Compact away the steps nobody needs (same order).
+    const uint64_t live = __ballot(mask != 0);
+    if (lane == 0) s_wcnt[wave] = __popcll(live);
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += s_wcnt[w];
+    const int n_steps = s_wcnt[0] + s_wcnt[1] + s_wcnt[2] + s_wcnt[3];
+    if (mask != 0) {
+      const int at = before + __popcll(live & ((uint64_t(1) << lane) - 1));
+      st.mask[at] = mask;
+      for (int u = 0; u < 4; ++u) st.slot[at][u] = sl[u];
+    }
+    __syncthreads();
+    // Two register sets: the tiles of step x + 2 are requested while step x
+    // runs, so each load has two steps to arrive before it is stored to LDS.
+    auto stage = [&](int x, v4f (&reg)[4]) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int32_t sv = st.slot[x][u];
+        if (sv >= 0) {
+          const float* src = (u < 2 ? pa : pb) + int64_t(sv) * kLeaf2 + srow * kLeaf + scol;
+          reg[u] = *reinterpret_cast<const v4f*>(src);
+        }
+      }
+    };
+    auto store = [&](int x, int buf, const v4f (&reg)[4]) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (st.slot[x][u] < 0) continue;
+        float* dst = u < 2 ? &s_a[buf][u][srow * kAStride + scol] : &s_b[buf][u - 2][srow * kLeaf + scol];
+        *reinterpret_cast<v4f*>(dst) = reg[u];
+      }
+    };
+    auto compute = [&](int x, int buf) {
+      if ((st.mask[x] >> wave) & 1) {
+        const int m = lane & 31, kk = lane >> 5;
+        F32Frag f;
+        const v4f* ar = reinterpret_cast<const v4f*>(&s_a[buf][a_own][m * kAStride + kk * 16]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) f.a[u] = ar[u];
+        const float* br = &s_b[buf][b_own][(kk * 16) * kLeaf + m];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) f.b[u] = br[u * kLeaf];
+        mma_f32(f, acc);
+      }
+    };
+    // One step: request step x + 2 into `ahead`, multiply step x from LDS,
+    // then move step x + 1 (requested a step earlier, in `next`) to LDS.
+    auto step = [&](int x, v4f (&ahead)[4], const v4f (&next)[4]) {
+      if (x + 2 < n_steps) stage(x + 2, ahead);
+      compute(x, x & 1);
+      if (x + 1 < n_steps) store(x + 1, (x + 1) & 1, next);
+      __syncthreads();
+    };
+    if (n_steps > 0) {
+      stage(0, r0);
+      if (n_steps > 1) stage(1, r1);
+      store(0, 0, r0);
+      __syncthreads();
+    }
+    for (int x = 0; x < n_steps; x += 2) {
+      step(x, r0, r1);
+      if (x + 1 < n_steps) step(x + 1, r1, r0);
+    }
+  }
+  // Epilogue: owner q writes its C block if it exists.
+  const int q = wave;
+  if (uniform(g.sup_cnt4[4 * p + q]) <= 0) return;
+  const int64_t node = uniform(g.sup_noff[4 * p + q]);
+  const int i = 2 * I + a_own, j = 2 * J + b_own;
+  float* out = static_cast<float*>(g.pool_c) + node * kLeaf2;
+  const float* xt = nullptr;
+  if (g.sp2) {
+    const int32_t sx = g.map_x[int64_t(i) * g.nb + j];
+    if (sx >= 0) xt = static_cast<const float*>(g.pool_x) + int64_t(sx) * kLeaf2;
+  }
+  const int col = lane & 31, kk = lane >> 5;
+  Epi<float> e;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = (r >> 2) * 8 + kk * 4 + (r & 3);
+    const float x = xt ? xt[row * kLeaf + col] : 0.0f;
+    out[row * kLeaf + col] = e.apply(acc[r], x, g.sp2, g.square, i == j && row == col);
+  }
+  e.finish(g, node, pack_ij(i, j), lane);
+}
+
+// ---- FP32 leaf products: one wave per 2 x 2 group, no barriers ---------------
+//
+// The same 2 x 2 groups and pass bits as k_leaf_gemm_f32_2x2, but one wave
+// owns all four C blocks (four accumulators) and loads its operands straight
+// into registers: per leaf k the (up to) two A tiles and two B tiles feed up
+// to four products, the next k's tiles are in flight while the current k's
+// products run, and waves never wait for each other.
+
+struct W2x2Frag {
+  v4f a[2][4];
+  float b[2][16];
+};
+
+__device__ inline void load_w2x2(const float* __restrict__ pa, const float* __restrict__ pb,
+                                 const int32_t (&sl)[4], int lane, W2x2Frag& f) {
+  const int m = lane & 31, kk = lane >> 5;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    if (sl[u] >= 0) {
+      const v4f* ar = reinterpret_cast<const v4f*>(pa + int64_t(sl[u]) * kLeaf2 + m * kLeaf + kk * 16);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) f.a[u][q] = ar[q];
+    }
+    if (sl[2 + u] >= 0) {
+      const float* br = pb + int64_t(sl[2 + u]) * kLeaf2 + (kk * 16) * kLeaf + m;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) f.b[u][q] = br[q * kLeaf];
+    }
+  }
+}
+
+__device__ inline void mma_pair(const v4f (&a)[4], const float (&b)[16], v16f& acc) {
+#pragma unroll
+  for (int s = 0; s < 16; ++s)
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a[s >> 2][s & 3], b[s], acc, 0, 0, 0);
+}
+
+__device__ inline void mma_w2x2(const W2x2Frag& f, int mask, v16f (&acc)[4]) {
+  if (mask & 1) mma_pair(f.a[0], f.b[0], acc[0]);
+  if (mask & 2) mma_pair(f.a[0], f.b[1], acc[1]);
+  if (mask & 4) mma_pair(f.a[1], f.b[0], acc[2]);
+  if (mask & 8) mma_pair(f.a[1], f.b[1], acc[3]);
+}
+
+constexpr int kWBatch = 32;            // list entries per slot batch (64 steps)
+
+// kAhead: operand sets in flight per wave (2: the next step's loads overlap
+// the current step's products; 1: other waves hide the latency).
+template <int kAhead>
+__global__ void __launch_bounds__(256) k_leaf_gemm_f32_w2x2(GemmArgs g) {
+  __shared__ int32_t s_tab[kWaves][5][2 * kWBatch];  // mask, 4 slots per step
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t p = uniform(xcd_contiguous_block() * kWaves + wave);
+  if (p >= g.n_super) return;
+  int32_t(*tab)[2 * kWBatch] = s_tab[wave];
+  const int32_t IJ = uniform(g.sup_nodes[p]);
+  const int I = unpack_i(IJ), J = unpack_j(IJ);
+  const float* pa = static_cast<const float*>(g.pool_a);
+  const float* pb = static_cast<const float*>(g.pool_b);
+  const int64_t e0 = uniform(g.sup_nptr[p]), e1 = uniform(g.sup_nptr[p + 1]);
+  v16f acc[4] = {};
+  W2x2Frag cur, nxt;
+  for (int64_t eb = e0; eb < e1; eb += kWBatch) {
+    // Steps of this batch: lane l takes entry l / 2, c = l % 2.
+    int32_t mask = 0, sl[4] = {-1, -1, -1, -1};
+    const int64_t e = eb + (lane >> 1);
+    if (e < e1) {
+      const int c = lane & 1;
+      const int bits = g.sup_bits[e];
+      for (int q = 0; q < 4; ++q) mask |= ((bits >> (2 * q + c)) & 1) << q;
+      const int k = 2 * g.sup_ks[e] + c;
+      if (mask & 0x3) sl[0] = g.map_a[int64_t(2 * I) * g.nb + k];
+      if (mask & 0xC) sl[1] = g.map_a[int64_t(2 * I + 1) * g.nb + k];
+      if (mask & 0x5) sl[2] = g.map_b[int64_t(k) * g.nb + 2 * J];
+      if (mask & 0xA) sl[3] = g.map_b[int64_t(k) * g.nb + 2 * J + 1];
+    }
+    const uint64_t live = __ballot(mask != 0);
+    const int n_steps = __popcll(live);
+    if (mask != 0) {
+      const int at = __popcll(live & ((uint64_t(1) << lane) - 1));
+      tab[0][at] = mask;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) tab[1 + u][at] = sl[u];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    auto slots = [&](int x, int32_t (&out)[4]) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) out[u] = __builtin_amdgcn_readfirstlane(tab[1 + u][x]);
+    };
+    auto step_mask = [&](int x) { return __builtin_amdgcn_readfirstlane(tab[0][x]); };
+    if (kAhead == 1) {
+      for (int x = 0; x < n_steps; ++x) {
+        int32_t s0[4];
+        slots(x, s0);
+        load_w2x2(pa, pb, s0, lane, cur);
+        mma_w2x2(cur, step_mask(x), acc);
+      }
+    } else if (n_steps > 0) {
+      int32_t s0[4];
+      slots(0, s0);
+      load_w2x2(pa, pb, s0, lane, cur);
+      int x = 0;
+      for (; x + 2 < n_steps; x += 2) {
+        int32_t s1[4], s2[4];
+        slots(x + 1, s1);
+        load_w2x2(pa, pb, s1, lane, nxt);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_w2x2(cur, step_mask(x), acc);
+        __builtin_amdgcn_sched_barrier(0);
+        slots(x + 2, s2);
+        load_w2x2(pa, pb, s2, lane, cur);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_w2x2(nxt, step_mask(x + 1), acc);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (x + 1 < n_steps) {
+        int32_t s1[4];
+        slots(x + 1, s1);
+        load_w2x2(pa, pb, s1, lane, nxt);
+        __builtin_amdgcn_sched_barrier(0);
+        mma_w2x2(cur, step_mask(x), acc);
+        mma_w2x2(nxt, step_mask(x + 1), acc);
+      } else {
+        mma_w2x2(cur, step_mask(x), acc);
+      }
+    }
+    // The table is rewritten by the next batch only after every lane's reads.
+    __builtin_amdgcn_wave_barrier();
+  }
+  const int col = lane & 31, kk = lane >> 5;
+  auto emit = [&](int q, const v16f& a) {
+    if (uniform(g.sup_cnt4[4 * p + q]) <= 0) return;
+    const int64_t node = uniform(g.sup_noff[4 * p + q]);
+    const int i = 2 * I + (q >> 1), j = 2 * J + (q & 1);
+    float* out = static_cast<float*>(g.pool_c) + node * kLeaf2;
+    const float* xt = nullptr;
+    if (g.sp2) {
+      const int32_t sx = g.map_x[int64_t(i) * g.nb + j];
+      if (sx >= 0) xt = static_cast<const float*>(g.pool_x) + int64_t(sx) * kLeaf2;
+    }
+    Epi<float> e;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int row = (r >> 2) * 8 + kk * 4 + (r & 3);
+      const float x = xt ? xt[row * kLeaf + col] : 0.0f;
+      out[row * kLeaf + col] = e.apply(a[r], x, g.sp2, g.square, i == j && row == col);
+    }
+    e.finish(g, node, pack_ij(i, j), lane);
+  };
+  emit(0, acc[0]);
+  emit(1, acc[1]);
+  emit(2, acc[2]);
+  emit(3, acc[3]);
+}
+
+// ---- FP32 leaf products on 4 x 4 groups of C blocks --------------------------
+//
+// One workgroup of 4 waves owns the 4 x 4 C blocks (4I + a, 4J + b) below a
+// tier-(d-2) node (I, J); wave a owns row a, four accumulators.  Its work
+// is the node's ascending K list, each entry carrying the 64 pass bits of
+// its leaf products (bit 16c + 4a + b, leaf k = 4K + c).  For every leaf k
+// in ascending order, the A tiles A_{4I+a,k} and B tiles B_{k,4J+b} that
+// some owner needs are loaded once into LDS, double-buffered, with the
+// tiles of step x + 2 requested while step x runs.  Each wave reads its A
+// tile once per step and multiplies it with the B tiles of its set bits:
+// a tile read from memory feeds up to four products, a quarter of the
+// operand traffic of one wave per C block.  Every C block still
+// accumulates over its own k in ascending order.
+
+constexpr int kQBatch = 32;            // list entries staged per batch
+constexpr int kQSteps = 4 * kQBatch;   // leaf steps per batch (c = 0..3)
+
+struct QuadTable {
+  int32_t mask[kQSteps];     // bit 4a + b: block (a, b) multiplies at this step
+  int32_t slot[kQSteps][8];  // A rows 0..3, B columns 0..3; -1 if unused
+};
+
+__global__ void __launch_bounds__(256) k_leaf_gemm_f32_4x4(GemmArgs g) {
+  __shared__ float s_a[2][4][kLeaf * kAStride];
+  __shared__ float s_b[2][4][kLeaf2];
+  __shared__ QuadTable st;
+  __shared__ int32_t s_wcnt[2];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t p = uniform(xcd_contiguous_block());
+  if (p >= g.n_quad) return;
+  const int32_t IJ = uniform(g.quad_nodes[p]);
+  const int I = unpack_i(IJ), J = unpack_j(IJ);
+  const float* pa = static_cast<const float*>(g.pool_a);
+  const float* pb = static_cast<const float*>(g.pool_b);
+  const int64_t e0 = uniform(g.quad_nptr[p]), e1 = uniform(g.quad_nptr[p + 1]);
+  const int srow = tid >> 3, scol = (tid & 7) * 4;
+  v16f acc0 = {}, acc1 = {}, acc2 = {}, acc3 = {};
+  v4f r0[8], r1[8];
+  for (int64_t eb = e0; eb < e1; eb += kQBatch) {
+    // Step table: thread x < kQSteps takes entry x / 4, c = x % 4.
+    int32_t mask = 0, sl[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sl[u] = -1;
+    if (tid < kQSteps) {
+      const int64_t e = eb + (tid >> 2);
+      if (e < e1) {
+        const int c = tid & 3;
+        mask = int32_t((g.quad_masks[e] >> (16 * c)) & 0xffff);
+        const int k = 4 * g.quad_ks[e] + c;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if ((mask >> (4 * u)) & 0xF) sl[u] = g.map_a[int64_t(4 * I + u) * g.nb + k];
+          if (mask & (0x1111 << u)) sl[4 + u] = g.map_b[int64_t(k) * g.nb + 4 * J + u];
+        }
+      }
+    }
+    const uint64_t live = __ballot(mask != 0);
+    if (lane == 0 && wave < 2) s_wcnt[wave] = __popcll(live);
+    __syncthreads();
+    const int n_steps = s_wcnt[0] + s_wcnt[1];
+    if (mask != 0) {
+      const int at = (wave == 1 ? s_wcnt[0] : 0) + __popcll(live & ((uint64_t(1) << lane) - 1));
+      st.mask[at] = mask;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) st.slot[at][u] = sl[u];
+    }
+    __syncthreads();
+    auto stage = [&](int x, v4f (&reg)[8]) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int32_t sv = st.slot[x][u];
+        if (sv >= 0) {
+          const float* src = (u < 4 ? pa : pb) + int64_t(sv) * kLeaf2 + srow * kLeaf + scol;
+          reg[u] = *reinterpret_cast<const v4f*>(src);
+        }
+      }
+    };
+    auto store = [&](int x, int buf, const v4f (&reg)[8]) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (st.slot[x][u] < 0) continue;
+        float* dst = u < 4 ? &s_a[buf][u][srow * kAStride + scol]
+                           : &s_b[buf][u - 4][srow * kLeaf + scol];
+        *reinterpret_cast<v4f*>(dst) = reg[u];
+      }
+    };
+    auto compute = [&](int x, int buf) {
+      const int row = (st.mask[x] >> (4 * wave)) & 0xF;
+      if (row == 0) return;
+      const int m = lane & 31, kk = lane >> 5;
+      F32Frag f;
+      const v4f* ar = reinterpret_cast<const v4f*>(&s_a[buf][wave][m * kAStride + kk * 16]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) f.a[u] = ar[u];
+      auto col = [&](int b, v16f& acc) {
+        const float* br = &s_b[buf][b][(kk * 16) * kLeaf + m];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) f.b[u] = br[u * kLeaf];
+        mma_f32(f, acc);
+      };
+      if (row & 1) col(0, acc0);
+      if (row & 2) col(1, acc1);
+      if (row & 4) col(2, acc2);
+      if (row & 8) col(3, acc3);
+    };
+    auto step = [&](int x, v4f (&ahead)[8], const v4f (&next)[8]) {
+      if (x + 2 < n_steps) stage(x + 2, ahead);
+      compute(x, x & 1);
+      if (x + 1 < n_steps) store(x + 1, (x + 1) & 1, next);
+      __syncthreads();
+    };
+    if (n_steps > 0) {
+      stage(0, r0);
+      if (n_steps > 1) stage(1, r1);
+      store(0, 0, r0);
+      __syncthreads();
+    }
+    for (int x = 0; x < n_steps; x += 2) {
+      step(x, r0, r1);
+      if (x + 1 < n_steps) step(x + 1, r1, r0);
+    }
+  }
+  // Epilogue: wave a writes the blocks of its row that exist in C.
+  const int i = 4 * I + wave;
+  const int col = lane & 31, kk = lane >> 5;
+  auto emit = [&](int b, const v16f& acc) {
+    const int j = 4 * J + b;
+    const int32_t node = uniform(g.map_c[int64_t(i) * g.nb + j]);
+    if (node < 0) return;
+    float* out = static_cast<float*>(g.pool_c) + int64_t(node) * kLeaf2;
+    const float* xt = nullptr;
+    if (g.sp2) {
+      const int32_t sx = g.map_x[int64_t(i) * g.nb + j];
+      if (sx >= 0) xt = static_cast<const float*>(g.pool_x) + int64_t(sx) * kLeaf2;
+    }
+    Epi<float> e;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int rr = (r >> 2) * 8 + kk * 4 + (r & 3);
+      const float x = xt ? xt[rr * kLeaf + col] : 0.0f;
+      out[rr * kLeaf + col] = e.apply(acc[r], x, g.sp2, g.square, i == j && rr == col);
+    }
+    e.finish(g, node, pack_ij(i, j), lane);
+  };
+  emit(0, acc0);
+  emit(1, acc1);
+  emit(2, acc2);
+  emit(3, acc3);
 }
 
 struct F64Frag {
@@ -166,26 +699,44 @@ __device__ inline void mma_f64(const F64Frag& f, v4d (&acc)[2][2]) {
 
 __global__ void __launch_bounds__(256) k_leaf_gemm_f64(GemmArgs g) {
   const int lane = threadIdx.x & 63;
-  const int64_t node = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+  const int64_t node = uniform(xcd_contiguous_block() * kWaves + (threadIdx.x >> 6));
   if (node >= g.n_nodes) return;
-  const int32_t ij = g.nodes[node];
+  const int32_t ij = uniform(g.nodes[node]);
   const int i = unpack_i(ij), j = unpack_j(ij);
   const double* pa = static_cast<const double*>(g.pool_a);
   const double* pb = static_cast<const double*>(g.pool_b);
-  const int64_t t0 = g.nptr[node], t1 = g.nptr[node + 1];
+  const int64_t t0 = uniform(g.nptr[node]), t1 = uniform(g.nptr[node + 1]);
   v4d acc[2][2] = {};
   F64Frag cur, nxt;
-  auto tile_a = [&](int64_t t) {
-    return pa + int64_t(g.map_a[int64_t(i) * g.nb + g.ks[t]]) * kLeaf2;
-  };
-  auto tile_b = [&](int64_t t) {
-    return pb + int64_t(g.map_b[int64_t(g.ks[t]) * g.nb + j]) * kLeaf2;
-  };
-  if (t0 < t1) load_f64(tile_a(t0), tile_b(t0), lane, cur);
-  for (int64_t t = t0; t < t1; ++t) {
-    if (t + 1 < t1) load_f64(tile_a(t + 1), tile_b(t + 1), lane, nxt);
-    mma_f64(cur, acc);
-    cur = nxt;
+  __shared__ int32_t s_slots[kWaves][128];
+  TaskSlots ts(g, i, j, t0, t1, s_slots[threadIdx.x >> 6], lane);
+  if (t0 < t1) {
+    // Two operand sets in alternation: the next product's loads are always
+    // in flight while the current product runs on the MFMA unit.  The loop
+    // body has no conditional loads, so the waits stay exact.
+    auto fetch = [&](int64_t t, F64Frag& f) {
+      ts.advance(t, lane);
+      load_f64(pa + ts.a(t) * kLeaf2, pb + ts.b(t) * kLeaf2, lane, f);
+    };
+    fetch(t0, cur);
+    int64_t t = t0;
+    for (; t + 2 < t1; t += 2) {
+      fetch(t + 1, nxt);
+      __builtin_amdgcn_sched_barrier(0);  // keep the loads ahead of the MFMAs
+      mma_f64(cur, acc);
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(t + 2, cur);
+      __builtin_amdgcn_sched_barrier(0);
+      mma_f64(nxt, acc);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (t + 1 < t1) {
+      fetch(t + 1, nxt);
+      mma_f64(cur, acc);
+      mma_f64(nxt, acc);
+    } else {
+      mma_f64(cur, acc);
+    }
   }
   double* out = static_cast<double*>(g.pool_c) + node * kLeaf2;
   const double* xt = nullptr;
@@ -253,6 +804,20 @@ __global__ void __launch_bounds__(256) k_sp2_rest(RestArgs r) {
   }
 }
 
+// Clears the per-iteration SP2 arrays in one launch.
+__global__ void k_sp2_prepare(int32_t* __restrict__ map, double* __restrict__ norm_leaf,
+                              double* __restrict__ err_part, int64_t cells,
+                              double* __restrict__ trace_part, int nb, int64_t* counter) {
+  for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < cells;
+       x += int64_t(gridDim.x) * blockDim.x) {
+    map[x] = -1;
+    norm_leaf[x] = 0.0;
+    err_part[x] = 0.0;
+    if (x < nb) trace_part[x] = 0.0;
+    if (x == 0) *counter = 0;
+  }
+}
+
 __global__ void __launch_bounds__(1024) k_sp2_reduce(int nb, const double* __restrict__ trace_part,
                                                      const double* __restrict__ err_part,
                                                      const double* __restrict__ norm_leaf,
@@ -287,8 +852,39 @@ __global__ void __launch_bounds__(1024) k_sp2_reduce(int nb, const double* __res
 
 }  // namespace
 
+// Leaf-product kernel: SPAMM_LEAF_KERNEL = block | 2x2 | 4x4 | w2x2 | w2x2s
+// picks one (all compute the same result, in the same order); unset or
+// unknown picks the default.
+int leaf_kernel_choice() {
+  const char* v = std::getenv("SPAMM_LEAF_KERNEL");
+  if (v == nullptr) return kLeafDefault;
+  if (std::strcmp(v, "w2x2") == 0) return kLeafW2x2;
+  if (std::strcmp(v, "w2x2s") == 0) return kLeafW2x2s;
+  if (std::strcmp(v, "block") == 0) return kLeafBlock;
+  if (std::strcmp(v, "2x2") == 0) return kLeaf2x2;
+  if (std::strcmp(v, "4x4") == 0) return kLeaf4x4;
+  return kLeafDefault;
+}
+
 void launch_leaf_gemm(int prec, const GemmArgs& g, hipStream_t s) {
   if (g.n_nodes <= 0) return;
+  const int choice = leaf_kernel_choice();
+  if (prec == SPAMM_FP32 && g.n_quad > 0 && choice == kLeaf4x4) {
+    k_leaf_gemm_f32_4x4<<<unsigned(g.n_quad), 256, 0, s>>>(g);
+    return;
+  }
+  if (prec == SPAMM_FP32 && g.n_super > 0 && (choice == kLeafW2x2 || choice == kLeafW2x2s)) {
+    const unsigned grid = unsigned((g.n_super + kWaves - 1) / kWaves);
+    if (choice == kLeafW2x2)
+      k_leaf_gemm_f32_w2x2<2><<<grid, 256, 0, s>>>(g);
+    else
+      k_leaf_gemm_f32_w2x2<1><<<grid, 256, 0, s>>>(g);
+    return;
+  }
+  if (prec == SPAMM_FP32 && g.n_super > 0 && (choice == kLeaf2x2 || choice == kLeaf4x4)) {
+    k_leaf_gemm_f32_2x2<<<unsigned(g.n_super), 256, 0, s>>>(g);
+    return;
+  }
   const unsigned grid = unsigned((g.n_nodes + kWaves - 1) / kWaves);
   if (prec == SPAMM_FP64)
     k_leaf_gemm_f64<<<grid, 64 * kWaves, 0, s>>>(g);
@@ -303,6 +899,13 @@ void launch_sp2_rest(int prec, const RestArgs& r, hipStream_t s) {
     k_sp2_rest<double><<<grid, 64 * kWaves, 0, s>>>(r);
   else
     k_sp2_rest<float><<<grid, 64 * kWaves, 0, s>>>(r);
+}
+
+void launch_sp2_prepare(int32_t* map, double* norm_leaf, double* err_part, int nb,
+                        double* trace_part, int64_t* counter, hipStream_t s) {
+  const int64_t cells = int64_t(nb) * nb;
+  const unsigned g = unsigned(std::min<int64_t>((cells + 255) / 256, 4096));
+  k_sp2_prepare<<<g, 256, 0, s>>>(map, norm_leaf, err_part, cells, trace_part, nb, counter);
 }
 
 void launch_sp2_reduce(int nb, const double* trace_part, const double* err_part,

@@ -363,3 +363,24 @@ def test_sp2_initial_guess_matches_oracle(torch_dev, lib, prec):
     # Leaf norms of the FP64 values of X_0, in either precision.
     for g, o in zip(lib.spamm_matrix_norms(x0), so.tier_norms(so.leaf_norms(ox))):
         np.testing.assert_allclose(g, o, rtol=1e-12)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_leaf_kernels_agree_bitwise(torch_dev, lib, prec, monkeypatch):
+    """Every leaf-product kernel (one wave per C block, 2 x 2 and 4 x 4 block
+    groups) adds the same products in the same ascending k order."""
+    w = water_cluster(40, 1.5, 3)
+    f = to_dev(torch_dev, w.f)
+    x0, _, _ = lib.sp2_initial_guess(f, prec)
+    out = {}
+    for kern in ("block", "2x2", "4x4", "w2x2", "w2x2s"):
+        monkeypatch.setenv("SPAMM_LEAF_KERNEL", kern)
+        c, st = lib.spamm_multiply(x0, x0, 1e-7)
+        p, s2 = lib.sp2_solve(f, w.n_occ, 1e-7, precision=prec, max_iter=6)
+        out[kern] = (lib.spamm_to_dense(c), st["n_exec"], p, s2["errors"])
+    ref = out["block"]
+    for kern in ("2x2", "4x4", "w2x2", "w2x2s"):
+        np.testing.assert_array_equal(out[kern][0], ref[0])
+        assert out[kern][1] == ref[1]
+        np.testing.assert_array_equal(out[kern][2], ref[2])
+        assert out[kern][3] == ref[3]
