@@ -96,7 +96,8 @@ typedef struct sp2_options {
     int32_t precision;   /* spamm_precision; default SPAMM_FP32 */
     int32_t max_iter;    /* 1..SP2_MAX_ITER; default 100 */
     int32_t min_iter;    /* no stop before this many iterations; default 0 */
-    int32_t stall_rule;  /* 1: stop when e_n >= e_{n-2} once e_n < stall_floor; default 1 */
+    int32_t stall_rule;  /* 1: stop when e_n >= e_{n-2} once
+                            e_n < stall_floor * sqrt(max(n_occ, 1)); default 1 */
     double tol;          /* stop when e_n = ||X~_n^2 - X_n||_F < tol; default 1e-8 */
     double stall_floor;  /* default 1e-3 */
 } sp2_options;

@@ -19,8 +19,10 @@ out.  The steps below are that scheme as read for this build:
      t_n = tr X_n;  C = SpAMM(X_n, X_n, tau);  e_n = ||C - X_n||_F
      X_{n+1} = C if t_n > n_occ else 2 X_n - C
      stop if e_n < tol (converged), or, with the stall rule on, if n >= 2,
-     e_n < stall_floor and e_n >= e_{n-2} (stalled at the precision floor,
-     the precision or culling floor), or when n + 1 = max_iter (not converged).
+     e_n < stall_floor * sqrt(max(n_occ, 1)) and e_n >= e_{n-2} (stalled at
+     the precision or culling floor, which grows with ||P||_F = sqrt(n_occ);
+     past it the iteration drifts and, in finite precision, eventually
+     diverges), or when n + 1 = max_iter (not converged).
    The returned projector is X_{n+1} of the stopping iteration.
    Stopping is only allowed once n + 1 >= min_iter.
 
@@ -30,6 +32,7 @@ recursive Alg. 1 form (`alg1.spamm_alg1`), which execute the same leaf set.
 from __future__ import annotations
 
 import dataclasses
+import math
 
 import numpy as np
 
@@ -87,6 +90,7 @@ def sp2(f: np.ndarray, n_occ: int, tau: float, tol: float = 1e-8, max_iter: int 
     if not eps_max > eps_min:
         raise ValueError("degenerate spectrum bounds")
     x = initial_x(f, eps_min, eps_max, n_pad)
+    floor = stall_floor * math.sqrt(max(n_occ, 1))
     branches, traces, errors, execs = [], [], [], []
     stop = STOP_MAX_ITER
     it = 0
@@ -104,7 +108,7 @@ def sp2(f: np.ndarray, n_occ: int, tau: float, tol: float = 1e-8, max_iter: int 
             if e < tol:
                 stop = STOP_CONVERGED
                 break
-            if stall and it >= 2 and e < stall_floor and e >= errors[it - 2]:
+            if stall and it >= 2 and e < floor and e >= errors[it - 2]:
                 stop = STOP_STALLED
                 break
     return SP2Result(p=x[:n, :n].copy(), iterations=it + 1, branches=branches, traces=traces,

@@ -724,6 +724,8 @@ Error sp2_impl(const double* f, int64_t n, int64_t ldf, int64_t n_occ, double ta
   }
   double t_n = w.ctl_host->sp2_trace;
   std::vector<double> errs;
+  // The stall rule acts below stall_floor * ||P||_F, ||P||_F = sqrt(n_occ).
+  const double stall_at = opt.stall_floor * std::sqrt(double(std::max<int64_t>(n_occ, 1)));
   int stop = SP2_STOP_MAX_ITER;
   int it = 0;
   int64_t total_exec = 0;
@@ -832,7 +834,7 @@ Error sp2_impl(const double* f, int64_t n, int64_t ldf, int64_t n_occ, double ta
         stop = SP2_STOP_CONVERGED;
         break;
       }
-      if (opt.stall_rule && it >= 2 && e_n < opt.stall_floor && e_n >= errs[it - 2]) {
+      if (opt.stall_rule && it >= 2 && e_n < stall_at && e_n >= errs[it - 2]) {
         stop = SP2_STOP_STALLED;
         break;
       }

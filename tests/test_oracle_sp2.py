@@ -40,6 +40,7 @@ def test_water_cluster_tau_zero_equals_eigh(molecules, seed):
 
 
 def scalar_sp2(lams, n_occ, tol, max_iter, stall_floor=1e-3):
+    floor = stall_floor * math.sqrt(max(n_occ, 1))
     """The same recurrence on the eigenvalues of X_0 (X_n is a polynomial in F)."""
     lam = np.array(lams, dtype=np.float64)
     bits, errs = [], []
@@ -52,7 +53,7 @@ def scalar_sp2(lams, n_occ, tol, max_iter, stall_floor=1e-3):
         errs.append(e)
         if e < tol:
             break
-        if it >= 2 and e < stall_floor and e >= errs[it - 2]:
+        if it >= 2 and e < floor and e >= errs[it - 2]:
             break
     return bits, errs
 
