@@ -54,10 +54,17 @@ typedef enum spamm_status {
 } spamm_status;
 
 /* Working precision of the stored leaf blocks and of the leaf products.
- * Norms, traces and the SP2 decisions are FP64 in every precision. */
+ * Norms, traces and the SP2 decisions are FP64 in every precision.  The
+ * 16-bit forms accumulate in FP32.  FP16 forms need |entries| <= 65504
+ * (inputs are not rescaled); a product that leaves that range fails with
+ * SPAMM_ERR_NONFINITE. */
 typedef enum spamm_precision {
     SPAMM_FP64 = 0,   /* FP64 tiles, FP64 MFMA products */
-    SPAMM_FP32 = 1    /* FP32 tiles, FP32 MFMA products, FP32 accumulation */
+    SPAMM_FP32 = 1,   /* FP32 tiles, FP32 MFMA products */
+    SPAMM_BF16 = 2,   /* BF16 tiles, BF16 MFMA products */
+    SPAMM_FP16 = 3,   /* FP16 tiles, FP16 MFMA products */
+    SPAMM_BF16X3 = 4, /* x = hi + lo in BF16; hi*hi + hi*lo + lo*hi on BF16 MFMA */
+    SPAMM_FP16X3 = 5  /* x = hi + lo/2^11 in FP16; hi*hi + (hi*lo + lo*hi)/2^11 on FP16 MFMA */
 } spamm_precision;
 
 #define SPAMM_LEAF 32            /* leaf block edge N_b (Sec. 3) */
@@ -99,7 +106,9 @@ typedef struct sp2_options {
     int32_t stall_rule;  /* 1: stop when e_n >= e_{n-2} once
                             e_n < stall_floor * sqrt(max(n_occ, 1)); default 1 */
     double tol;          /* stop when e_n = ||X~_n^2 - X_n||_F < tol; default 1e-8 */
-    double stall_floor;  /* default 1e-3 */
+    double stall_floor;  /* default 0: max(1e-3, 4 u), u the leaf precision's unit
+                            roundoff (FP64 2^-53, FP32 2^-24, BF16 2^-8, FP16 2^-11,
+                            BF16X3 2^-16, FP16X3 2^-22) */
 } sp2_options;
 
 enum { SP2_STOP_CONVERGED = 0, SP2_STOP_STALLED = 1, SP2_STOP_MAX_ITER = 2 };

@@ -16,8 +16,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libspamm.so")
 
-FP64, FP32 = 0, 1
-PRECISIONS = {"fp64": FP64, "fp32": FP32}
+FP64, FP32, BF16, FP16, BF16X3, FP16X3 = 0, 1, 2, 3, 4, 5
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "fp16": FP16, "bf16x3": BF16X3,
+              "fp16x3": FP16X3}
 SP2_MAX_ITER = 256
 N_PHASES = 6
 PHASES = ("tree", "pyramid", "cull", "gemm", "epilogue", "dense")
@@ -258,7 +259,7 @@ def spamm_matrix_norms(m: SpammMatrix, stream=None) -> list:
 
 
 def sp2_options(precision="fp32", max_iter=100, min_iter=0, stall_rule=True, tol=1e-8,
-                stall_floor=1e-3) -> Sp2Options:
+                stall_floor=0.0) -> Sp2Options:
     o = Sp2Options()
     load().sp2_options_default(ctypes.byref(o))
     o.precision = PRECISIONS.get(precision, precision)

@@ -145,7 +145,7 @@ Workspace& ws() {
   return *g_ws_ptr;
 }
 
-bool valid_prec(int p) { return p == SPAMM_FP64 || p == SPAMM_FP32; }
+bool valid_prec(int p) { return p >= SPAMM_FP64 && p <= SPAMM_FP16X3; }
 
 // ---- matrices ----------------------------------------------------------------
 
@@ -175,6 +175,10 @@ Error build_from_dense(const double* a_dev, int64_t lda, int64_t n, int prec, Sc
   if (scale_host->nonfinite) {
     free_matrix(m);
     return err(SPAMM_ERR_NONFINITE, "input holds NaN or Inf");
+  }
+  if ((prec == SPAMM_FP16 || prec == SPAMM_FP16X3) && scale_host->max_val > 65504.0) {
+    free_matrix(m);
+    return err(SPAMM_ERR_INVALID_ARG, "FP16 forms need |entries| <= 65504");
   }
   m->n_blocks = cnt.count[0];
   e = alloc_pool(m, std::max<int64_t>(m->n_blocks, 1), s);
@@ -247,11 +251,26 @@ Error multiply_impl(const spamm_matrix* a, const spamm_matrix* b, double tau, hi
   g.map_c = c->map;
   g.coords_c = c->coords;
   g.norm_c = c->norms + tier_offset(c->depth);
+  const bool fp16 = a->prec == SPAMM_FP16 || a->prec == SPAMM_FP16X3;
+  int32_t* overflow = reinterpret_cast<int32_t*>(&ws().cull.ctl_dev->scratch[2]);
+  if (fp16) {
+    launch_fill_i32(overflow, 2, 0, s);
+    g.overflow = overflow;
+  }
   {
     PhaseTimer timer(SPAMM_PHASE_GEMM, s, cr.n_tasks);
     launch_leaf_gemm(a->prec, g, s);
   }
   launch_pyramid(c, s);
+  if (fp16) {
+    int32_t flag = 0;
+    Error e2 = read_small(&flag, overflow, sizeof(flag), s);
+    if (e2.ok() && flag) e2 = err(SPAMM_ERR_NONFINITE, "product leaves FP16's finite range");
+    if (!e2.ok()) {
+      free_matrix(c);
+      return e2;
+    }
+  }
   if (st) {
     st->n_exec = cr.n_tasks;
     st->n_cblocks = cr.n_cblocks;
@@ -394,7 +413,7 @@ void sp2_options_default(sp2_options* o) {
   o->min_iter = 0;
   o->stall_rule = 1;
   o->tol = 1e-8;
-  o->stall_floor = 1e-3;
+  o->stall_floor = 0.0;
 }
 
 const char* spamm_last_error(void) { return g_last_error.c_str(); }
@@ -724,8 +743,15 @@ Error sp2_impl(const double* f, int64_t n, int64_t ldf, int64_t n_occ, double ta
   }
   double t_n = w.ctl_host->sp2_trace;
   std::vector<double> errs;
-  // The stall rule acts below stall_floor * ||P||_F, ||P||_F = sqrt(n_occ).
-  const double stall_at = opt.stall_floor * std::sqrt(double(std::max<int64_t>(n_occ, 1)));
+  // The stall rule acts below stall_floor * ||P||_F, ||P||_F = sqrt(n_occ);
+  // stall_floor = 0 picks max(1e-3, 4 u) for the leaf precision's unit
+  // roundoff u, since the floor of e_n grows with u.
+  double floor_rel = opt.stall_floor;
+  if (floor_rel == 0.0) {
+    static const double unit[] = {0x1p-53, 0x1p-24, 0x1p-8, 0x1p-11, 0x1p-16, 0x1p-22};
+    floor_rel = std::max(1e-3, 4.0 * unit[opt.precision]);
+  }
+  const double stall_at = floor_rel * std::sqrt(double(std::max<int64_t>(n_occ, 1)));
   int stop = SP2_STOP_MAX_ITER;
   int it = 0;
   int64_t total_exec = 0;
@@ -777,6 +803,7 @@ Error sp2_impl(const double* f, int64_t n, int64_t ldf, int64_t n_occ, double ta
     g.map_x = x->map;
     g.trace_part = buf.trace_part;
     g.err_part = buf.err_part;
+    g.overflow = reinterpret_cast<int32_t*>(&ctl->scratch[2]);
     {
       PhaseTimer timer(SPAMM_PHASE_GEMM, s, cr.n_tasks);
       launch_leaf_gemm(opt.precision, g, s);
@@ -821,6 +848,11 @@ Error sp2_impl(const double* f, int64_t n, int64_t ldf, int64_t n_occ, double ta
       free_matrix(y);
       free_matrix(x);
       return e;
+    }
+    if (w.ctl_host->scratch[2] != 0) {
+      free_matrix(y);
+      free_matrix(x);
+      return err(SPAMM_ERR_NONFINITE, "SP2 iterate is not finite or leaves FP16's range");
     }
     const double e_n = std::sqrt(w.ctl_host->sp2_err2);
     t_n = w.ctl_host->sp2_trace;

@@ -24,8 +24,17 @@ constexpr int kMaxTiers = SPAMM_MAX_DEPTH + 1;
 
 __host__ __device__ inline int64_t tier_offset(int t) { return ((int64_t(1) << (2 * t)) - 1) / 3; }
 inline int64_t norms_size(int depth) { return tier_offset(depth + 1); }
-inline size_t elem_bytes(int prec) { return prec == SPAMM_FP64 ? 8 : 4; }
-inline size_t tile_bytes(int prec) { return kLeaf2 * elem_bytes(prec); }
+// Bytes of one stored 32 x 32 tile: FP64 8 KiB, FP32 4 KiB; 16-bit forms keep
+// the block and its transpose (4 KiB), split forms also the low part (8 KiB).
+inline size_t tile_bytes(int prec) {
+  switch (prec) {
+    case SPAMM_FP64: return 8 * kLeaf2;
+    case SPAMM_FP32: return 4 * kLeaf2;
+    case SPAMM_BF16:
+    case SPAMM_FP16: return 2 * 2 * kLeaf2;
+    default: return 4 * 2 * kLeaf2;
+  }
+}
 
 __host__ __device__ inline int32_t pack_ij(int i, int j) { return (i << 16) | j; }
 __host__ __device__ inline int unpack_i(int32_t p) { return p >> 16; }
@@ -107,6 +116,7 @@ struct Scale {
   double diag, sign, div;
   double eps_min, eps_max;
   double max_abs, max_asym;
+  double max_val;  // max |scaled value| (for the 16-bit range check)
   int32_t nonfinite;
   int32_t bad_bounds;
 };
@@ -265,6 +275,8 @@ struct GemmArgs {
   const int32_t* map_x;
   double* trace_part;    // [nb]
   double* err_part;      // [nb * nb]
+  // FP16 forms: set to 1 when a stored value leaves FP16's finite range.
+  int32_t* overflow;
 };
 // Leaf-product kernels (all add the same products in the same order):
 //   block  one wave per C block;
@@ -277,6 +289,8 @@ enum { kLeafBlock = 0, kLeaf2x2 = 1, kLeaf4x4 = 2, kLeafW2x2 = 3, kLeafW2x2s = 4
        kLeafDefault = kLeafW2x2s };
 int leaf_kernel_choice();
 void launch_leaf_gemm(int prec, const GemmArgs& g, hipStream_t s);
+// 16-bit forms (leafgemm16.hip).
+void launch_leaf_gemm_half(int prec, const GemmArgs& g, hipStream_t s);
 
 // SP2: blocks of X_n without any executed product.
 struct RestArgs {
@@ -295,6 +309,7 @@ struct RestArgs {
   int64_t* counter;      // appended blocks
 };
 void launch_sp2_rest(int prec, const RestArgs& r, hipStream_t s);
+void launch_sp2_rest_half(int prec, const RestArgs& r, hipStream_t s);
 // map(-1), leaf norms, err_part (nb*nb), trace_part (nb) and the counter
 // cleared for one SP2 iteration.
 void launch_sp2_prepare(int32_t* map, double* norm_leaf, double* err_part, int nb,

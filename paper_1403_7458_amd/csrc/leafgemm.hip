@@ -22,6 +22,7 @@
 #include <cstdlib>
 #include <cstring>
 
+#include "device_util.h"
 #include "internal.h"
 
 namespace spamm {
@@ -33,32 +34,6 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 4;
-constexpr int kXcds = 8;
-
-// Workgroups are dispatched to the 8 XCDs round-robin; renumber them so
-// that each XCD (and its L2) works through one contiguous range of the
-// Morton-ordered C blocks, whose A rows and B columns overlap.
-__device__ inline int64_t xcd_contiguous_block() {
-  const int64_t g = gridDim.x, b = blockIdx.x;
-  const int64_t x = b % kXcds, r = b / kXcds;
-  const int64_t q = g / kXcds, rem = g % kXcds;
-  return x * q + min(x, rem) + r;
-}
-
-// Wave-uniform copies (scalar registers), so that loops over a C block's
-// tasks compile to scalar branches with exact memory waits.
-__device__ inline int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ inline int64_t uniform(int64_t v) {
-  const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
-  const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
-  return int64_t((uint64_t(hi) << 32) | lo);
-}
-
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
 // Epilogue shared by both precisions: value c at (row, col) of C block
 // (i, j).  Plain product: store c.  SP2: X_{n+1} = c or 2 x - c, plus the
 // block's ||X_{n+1}||^2, ||C - X_n||^2 and diagonal sum.
@@ -814,7 +789,10 @@ __global__ void k_sp2_prepare(int32_t* __restrict__ map, double* __restrict__ no
     norm_leaf[x] = 0.0;
     err_part[x] = 0.0;
     if (x < nb) trace_part[x] = 0.0;
-    if (x == 0) *counter = 0;
+    if (x == 0) {
+      counter[0] = 0;  // blocks carried over by the 2X - X^2 branch
+      counter[1] = 0;  // FP16 overflow flag
+    }
   }
 }
 
@@ -868,6 +846,10 @@ int leaf_kernel_choice() {
 
 void launch_leaf_gemm(int prec, const GemmArgs& g, hipStream_t s) {
   if (g.n_nodes <= 0) return;
+  if (prec != SPAMM_FP64 && prec != SPAMM_FP32) {
+    launch_leaf_gemm_half(prec, g, s);
+    return;
+  }
   const int choice = leaf_kernel_choice();
   if (prec == SPAMM_FP32 && g.n_quad > 0 && choice == kLeaf4x4) {
     k_leaf_gemm_f32_4x4<<<unsigned(g.n_quad), 256, 0, s>>>(g);
@@ -894,6 +876,10 @@ void launch_leaf_gemm(int prec, const GemmArgs& g, hipStream_t s) {
 
 void launch_sp2_rest(int prec, const RestArgs& r, hipStream_t s) {
   if (r.n_x <= 0) return;
+  if (prec != SPAMM_FP64 && prec != SPAMM_FP32) {
+    launch_sp2_rest_half(prec, r, s);
+    return;
+  }
   const unsigned grid = unsigned((r.n_x + kWaves - 1) / kWaves);
   if (prec == SPAMM_FP64)
     k_sp2_rest<double><<<grid, 64 * kWaves, 0, s>>>(r);

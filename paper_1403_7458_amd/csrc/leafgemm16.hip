@@ -1,0 +1,349 @@
+// Leaf products of the 16-bit forms (BF16, FP16 and their split hi + lo
+// variants) on the MFMA units, with FP32 accumulation and the SP2 update
+// fused into the epilogue.  Tile formats are described in half.h.
+//
+// v_mfma_f32_32x32x16_{bf16,f16}: lane l supplies 8 consecutive k of row
+// l % 32 of A (and of column l % 32 of B); two instructions cover the 32 k
+// of a leaf product.  Step s of lane half kk takes k = 16 kk + 8 s .. + 7,
+// so a lane's A operands are the 32 contiguous bytes of row m from k = 16 kk
+// (part 0 / 2 of the tile) and its B operands the same run of row n of the
+// transposed tile (part 1 / 3).  The output layout is that of the FP32
+// 32x32 instructions.  The split forms add hi*lo + lo*hi into a second
+// accumulator, scaled by 2^-L once at the end.
+//
+// Ownership and order are those of the FP32 kernels: one wave per 2 x 2
+// group of C blocks (or one per C block when the tree has one tier), each C
+// block accumulated over its own k in ascending order.
+#include "device_util.h"
+#include "half.h"
+#include "internal.h"
+
+namespace spamm {
+
+namespace {
+
+typedef float v16f __attribute__((ext_vector_type(16)));
+
+constexpr int kWaves = 4;
+constexpr int kWBatch = 32;  // list entries per slot batch (64 steps)
+
+template <int P>
+struct HFrag {
+  typedef typename Half<P>::V V;
+  V hi[2];
+  V lo[2];  // split forms only
+};
+
+template <int P>
+__device__ inline void load_frag(const typename Half<P>::T* tile, int part, int lane, HFrag<P>& f) {
+  typedef typename Half<P>::V V;
+  const int m = lane & 31, kk = lane >> 5;
+  const V* p = reinterpret_cast<const V*>(tile + half_part(part) + m * kLeaf + 16 * kk);
+  f.hi[0] = p[0];
+  f.hi[1] = p[1];
+  if (is_split(P)) {
+    const V* q = reinterpret_cast<const V*>(tile + half_part(part + 2) + m * kLeaf + 16 * kk);
+    f.lo[0] = q[0];
+    f.lo[1] = q[1];
+  }
+}
+
+template <int P>
+__device__ inline v16f mfma16(typename Half<P>::V a, typename Half<P>::V b, v16f c) {
+  if constexpr (is_bf16(P))
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
+// acc.hh += A_hi B_hi; acc.x += A_hi B_lo + A_lo B_hi (split forms only).
+template <int P, bool kSplit = is_split(P)>
+struct HAcc {
+  v16f hh = {};
+  v16f x = {};
+  __device__ inline void add(const HFrag<P>& a, const HFrag<P>& b) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) hh = mfma16<P>(a.hi[s], b.hi[s], hh);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      x = mfma16<P>(a.hi[s], b.lo[s], x);
+      x = mfma16<P>(a.lo[s], b.hi[s], x);
+    }
+  }
+  __device__ inline float value(int r) const { return hh[r] + x[r] * (1.0f / lo_scale(P)); }
+};
+template <int P>
+struct HAcc<P, false> {
+  v16f hh = {};
+  __device__ inline void add(const HFrag<P>& a, const HFrag<P>& b) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s) hh = mfma16<P>(a.hi[s], b.hi[s], hh);
+  }
+  __device__ inline float value(int r) const { return hh[r]; }
+};
+
+// Epilogue: value c of C block (i, j) -> stored tile (hi, lo and their
+// transposes), SP2 update, FP64 norm, trace and ||C - X_n||^2 partials.
+template <int P>
+__device__ inline void epilogue(const GemmArgs& g, int64_t node, int i, int j, const HAcc<P>& acc,
+                                int lane) {
+  typedef typename Half<P>::T T;
+  const int stride = (is_split(P) ? 4 : 2) * kLeaf2;
+  T* out = static_cast<T*>(g.pool_c) + node * stride;
+  const T* xt = nullptr;
+  if (g.sp2) {
+    const int32_t sx = g.map_x[int64_t(i) * g.nb + j];
+    if (sx >= 0) xt = static_cast<const T*>(g.pool_x) + int64_t(sx) * stride;
+  }
+  const int col = lane & 31, kk = lane >> 5;
+  double nrm = 0.0, err = 0.0, tr = 0.0;
+  bool over = false;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = (r >> 2) * 8 + kk * 4 + (r & 3);
+    const float c = acc.value(r);
+    float v = c;
+    if (g.sp2) {
+      const double x =
+          xt ? decode_half<P>(xt[row * kLeaf + col],
+                              is_split(P) ? xt[half_part(2) + row * kLeaf + col] : T(0.0f))
+             : 0.0;
+      v = g.square ? c : float(2.0 * x - double(c));
+      const double d = double(c) - x;
+      err += d * d;
+    }
+    over |= !(fabsf(v) <= float(half_max(P)));
+    T hi, lo;
+    encode_half<P>(double(v), hi, lo);
+    out[row * kLeaf + col] = hi;
+    out[half_part(1) + col * kLeaf + row] = hi;
+    if (is_split(P)) {
+      out[half_part(2) + row * kLeaf + col] = lo;
+      out[half_part(3) + col * kLeaf + row] = lo;
+    }
+    const double stored = decode_half<P>(hi, lo);
+    nrm += stored * stored;
+    if (i == j && row == col) tr += stored;
+  }
+  const double n2 = wave_sum(nrm);
+  const double e2 = g.sp2 ? wave_sum(err) : 0.0;
+  const double t = (g.sp2 && i == j) ? wave_sum(tr) : 0.0;
+  const bool any_over = __ballot(over) != 0;
+  if (lane == 0) {
+    const int64_t cell = int64_t(i) * g.nb + j;
+    g.norm_c[cell] = sqrt(n2);
+    g.map_c[cell] = int32_t(node);
+    g.coords_c[node] = pack_ij(i, j);
+    if (g.sp2) {
+      g.err_part[cell] = e2;
+      if (i == j) g.trace_part[i] = t;
+    }
+    if (any_over && g.overflow) *g.overflow = 1;
+  }
+}
+
+// One wave per 2 x 2 group of C blocks (tier d-1 node), operands in
+// registers, the next step's tiles in flight during the current products.
+template <int P>
+__global__ void __launch_bounds__(256) k_leaf_gemm_half_w2x2(GemmArgs g) {
+  typedef typename Half<P>::T T;
+  __shared__ int32_t s_tab[kWaves][5][2 * kWBatch];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t p = uniform(xcd_contiguous_block() * kWaves + wave);
+  if (p >= g.n_super) return;
+  int32_t(*tab)[2 * kWBatch] = s_tab[wave];
+  const int32_t IJ = uniform(g.sup_nodes[p]);
+  const int I = unpack_i(IJ), J = unpack_j(IJ);
+  const int stride = (is_split(P) ? 4 : 2) * kLeaf2;
+  const T* pa = static_cast<const T*>(g.pool_a);
+  const T* pb = static_cast<const T*>(g.pool_b);
+  const int64_t e0 = uniform(g.sup_nptr[p]), e1 = uniform(g.sup_nptr[p + 1]);
+  HAcc<P> acc[4];
+  HFrag<P> fa[2][2], fb[2][2];  // [set][row or column]
+  for (int64_t eb = e0; eb < e1; eb += kWBatch) {
+    int32_t mask = 0, sl[4] = {-1, -1, -1, -1};
+    const int64_t e = eb + (lane >> 1);
+    if (e < e1) {
+      const int c = lane & 1;
+      const int bits = g.sup_bits[e];
+      for (int q = 0; q < 4; ++q) mask |= ((bits >> (2 * q + c)) & 1) << q;
+      const int k = 2 * g.sup_ks[e] + c;
+      if (mask & 0x3) sl[0] = g.map_a[int64_t(2 * I) * g.nb + k];
+      if (mask & 0xC) sl[1] = g.map_a[int64_t(2 * I + 1) * g.nb + k];
+      if (mask & 0x5) sl[2] = g.map_b[int64_t(k) * g.nb + 2 * J];
+      if (mask & 0xA) sl[3] = g.map_b[int64_t(k) * g.nb + 2 * J + 1];
+    }
+    const uint64_t live = __ballot(mask != 0);
+    const int n_steps = __popcll(live);
+    if (mask != 0) {
+      const int at = __popcll(live & ((uint64_t(1) << lane) - 1));
+      tab[0][at] = mask;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) tab[1 + u][at] = sl[u];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    auto fetch = [&](int x, HFrag<P> (&ra)[2], HFrag<P> (&rb)[2]) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int32_t sa = __builtin_amdgcn_readfirstlane(tab[1 + u][x]);
+        const int32_t sb = __builtin_amdgcn_readfirstlane(tab[3 + u][x]);
+        if (sa >= 0) load_frag<P>(pa + int64_t(sa) * stride, 0, lane, ra[u]);
+        if (sb >= 0) load_frag<P>(pb + int64_t(sb) * stride, 1, lane, rb[u]);
+      }
+    };
+    auto compute = [&](int x, const HFrag<P> (&ra)[2], const HFrag<P> (&rb)[2]) {
+      const int m = __builtin_amdgcn_readfirstlane(tab[0][x]);
+      if (m & 1) acc[0].add(ra[0], rb[0]);
+      if (m & 2) acc[1].add(ra[0], rb[1]);
+      if (m & 4) acc[2].add(ra[1], rb[0]);
+      if (m & 8) acc[3].add(ra[1], rb[1]);
+    };
+    if (n_steps > 0) {
+      fetch(0, fa[0], fb[0]);
+      int x = 0;
+      for (; x + 2 < n_steps; x += 2) {
+        fetch(x + 1, fa[1], fb[1]);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(x, fa[0], fb[0]);
+        __builtin_amdgcn_sched_barrier(0);
+        fetch(x + 2, fa[0], fb[0]);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(x + 1, fa[1], fb[1]);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (x + 1 < n_steps) {
+        fetch(x + 1, fa[1], fb[1]);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(x, fa[0], fb[0]);
+        compute(x + 1, fa[1], fb[1]);
+      } else {
+        compute(x, fa[0], fb[0]);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (uniform(g.sup_cnt4[4 * p + q]) <= 0) continue;
+    epilogue<P>(g, uniform(g.sup_noff[4 * p + q]), 2 * I + (q >> 1), 2 * J + (q & 1), acc[q], lane);
+  }
+}
+
+// One wave per C block over the leaf task list (trees of one tier).
+template <int P>
+__global__ void __launch_bounds__(256) k_leaf_gemm_half_block(GemmArgs g) {
+  typedef typename Half<P>::T T;
+  const int lane = threadIdx.x & 63;
+  const int64_t node = uniform(int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6));
+  if (node >= g.n_nodes) return;
+  const int32_t ij = uniform(g.nodes[node]);
+  const int i = unpack_i(ij), j = unpack_j(ij);
+  const int stride = (is_split(P) ? 4 : 2) * kLeaf2;
+  const T* pa = static_cast<const T*>(g.pool_a);
+  const T* pb = static_cast<const T*>(g.pool_b);
+  const int64_t t0 = uniform(g.nptr[node]), t1 = uniform(g.nptr[node + 1]);
+  HAcc<P> acc;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int k = uniform(g.ks[t]);
+    const int32_t sa = uniform(g.map_a[int64_t(i) * g.nb + k]);
+    const int32_t sb = uniform(g.map_b[int64_t(k) * g.nb + j]);
+    HFrag<P> fa, fb;
+    load_frag<P>(pa + int64_t(sa) * stride, 0, lane, fa);
+    load_frag<P>(pb + int64_t(sb) * stride, 1, lane, fb);
+    acc.add(fa, fb);
+  }
+  epilogue<P>(g, node, i, j, acc, lane);
+}
+
+// SP2 blocks of X_n with no executed product (see k_sp2_rest).
+template <int P>
+__global__ void __launch_bounds__(256) k_sp2_rest_half(RestArgs r) {
+  typedef typename Half<P>::T T;
+  const int lane = threadIdx.x & 63;
+  const int64_t s = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+  if (s >= r.n_x) return;
+  const int32_t ij = r.coords_x[s];
+  const int i = unpack_i(ij), j = unpack_j(ij);
+  const int64_t cell = int64_t(i) * r.nb + j;
+  if (r.map_out[cell] >= 0) return;
+  const int stride = (is_split(P) ? 4 : 2) * kLeaf2;
+  const T* x = static_cast<const T*>(r.pool_x) + s * stride;
+  double e = 0.0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int el = q * 64 + lane;
+    const double v = decode_half<P>(x[el], is_split(P) ? x[half_part(2) + el] : T(0.0f));
+    e += v * v;
+  }
+  e = wave_sum(e);
+  if (lane == 0) r.err_part[cell] = e;
+  if (r.square) return;
+  int64_t slot = 0;
+  if (lane == 0)
+    slot = r.base_slot + atomicAdd(reinterpret_cast<unsigned long long*>(r.counter), 1ull);
+  slot = __shfl(slot, 0, 64);
+  T* out = static_cast<T*>(r.pool_out) + slot * stride;
+  double nrm = 0.0, tr = 0.0;
+  // Doubling is exact in both parts, so the transposes are copied as well.
+#pragma unroll
+  for (int q = 0; q < 16 * (is_split(P) ? 4 : 2); ++q) {
+    const int el = q * 64 + lane;
+    out[el] = T(2.0f * float(x[el]));
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int el = q * 64 + lane;
+    const double v = 2.0 * decode_half<P>(x[el], is_split(P) ? x[half_part(2) + el] : T(0.0f));
+    nrm += v * v;
+    if (i == j && (el >> 5) == (el & 31)) tr += v;
+  }
+  nrm = wave_sum(nrm);
+  if (i == j) tr = wave_sum(tr);
+  if (lane == 0) {
+    r.map_out[cell] = int32_t(slot);
+    r.coords_out[slot] = ij;
+    r.norm_out[cell] = sqrt(nrm);
+    if (i == j) r.trace_part[i] = tr;
+  }
+}
+
+template <int P>
+void launch_p(const GemmArgs& g, hipStream_t s) {
+  if (g.n_super > 0)
+    k_leaf_gemm_half_w2x2<P><<<unsigned((g.n_super + kWaves - 1) / kWaves), 256, 0, s>>>(g);
+  else
+    k_leaf_gemm_half_block<P><<<unsigned((g.n_nodes + kWaves - 1) / kWaves), 256, 0, s>>>(g);
+}
+
+template <int P>
+void launch_rest_p(const RestArgs& r, hipStream_t s) {
+  k_sp2_rest_half<P><<<unsigned((r.n_x + kWaves - 1) / kWaves), 256, 0, s>>>(r);
+}
+
+}  // namespace
+
+void launch_leaf_gemm_half(int prec, const GemmArgs& g, hipStream_t s) {
+  if (g.n_nodes <= 0) return;
+  switch (prec) {
+    case SPAMM_BF16: launch_p<SPAMM_BF16>(g, s); break;
+    case SPAMM_FP16: launch_p<SPAMM_FP16>(g, s); break;
+    case SPAMM_BF16X3: launch_p<SPAMM_BF16X3>(g, s); break;
+    case SPAMM_FP16X3: launch_p<SPAMM_FP16X3>(g, s); break;
+    default: break;
+  }
+}
+
+void launch_sp2_rest_half(int prec, const RestArgs& r, hipStream_t s) {
+  if (r.n_x <= 0) return;
+  switch (prec) {
+    case SPAMM_BF16: launch_rest_p<SPAMM_BF16>(r, s); break;
+    case SPAMM_FP16: launch_rest_p<SPAMM_FP16>(r, s); break;
+    case SPAMM_BF16X3: launch_rest_p<SPAMM_BF16X3>(r, s); break;
+    case SPAMM_FP16X3: launch_rest_p<SPAMM_FP16X3>(r, s); break;
+    default: break;
+  }
+}
+
+}  // namespace spamm

@@ -4,6 +4,7 @@
 // 64-lane wave owns one 32 x 32 block and touches it in 128-byte row segments.
 #include <cmath>
 
+#include "half.h"
 #include "internal.h"
 
 namespace spamm {
@@ -36,7 +37,7 @@ __global__ void __launch_bounds__(256) k_leaf_norms_dense(const double* __restri
   if (blk >= int64_t(nb) * nb) return;
   const int bi = int(blk / nb), bj = int(blk % nb);
   const Scale sc = *scale;
-  double s = 0.0;
+  double s = 0.0, mx = 0.0;
   bool bad = false;
   const int64_t r0 = int64_t(bi) * kLeaf, c = int64_t(bj) * kLeaf + (lane & 31);
   if (r0 < n && int64_t(bj) * kLeaf < n) {
@@ -47,12 +48,19 @@ __global__ void __launch_bounds__(256) k_leaf_norms_dense(const double* __restri
         const double v = scaled(a, lda, r, c, sc);
         bad |= !isfinite(v);
         s += v * v;
+        mx = fmax(mx, fabs(v));
       }
     }
   }
   s = wave_sum(s);
+  mx = wave_max(mx);
   if (bad) scale->nonfinite = 1;
-  if (lane == 0) leaf[blk] = sqrt(s);
+  if (lane == 0) {
+    leaf[blk] = sqrt(s);
+    if (mx > 0.0)
+      atomicMax(reinterpret_cast<unsigned long long*>(&scale->max_val),
+                static_cast<unsigned long long>(__double_as_longlong(mx)));
+  }
 }
 
 __global__ void k_nonzero_flags(const double* __restrict__ leaf, int64_t m,
@@ -100,6 +108,71 @@ __global__ void __launch_bounds__(256) k_write_tiles(const double* __restrict__ 
   if (trace_part != nullptr && bi == bj) {
     tr = wave_sum(tr);
     if (lane == 0) trace_part[bi] = tr;
+  }
+}
+
+// 16-bit forms: hi (+ lo) and their transposes (layout in half.h).
+template <int P>
+__global__ void __launch_bounds__(256) k_write_tiles_half(const double* __restrict__ a, int64_t lda,
+                                                          int64_t n, int64_t n_blocks,
+                                                          const int32_t* __restrict__ coords,
+                                                          void* __restrict__ pool_v,
+                                                          const Scale* scale,
+                                                          double* __restrict__ trace_part) {
+  typedef typename Half<P>::T T;
+  const int lane = threadIdx.x & 63;
+  const int64_t slot = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (slot >= n_blocks) return;
+  const int32_t ij = coords[slot];
+  const int bi = unpack_i(ij), bj = unpack_j(ij);
+  const Scale sc = *scale;
+  T* tile = static_cast<T*>(pool_v) + slot * (is_split(P) ? 4 : 2) * kLeaf2;
+  double tr = 0.0;
+  const int col = lane & 31;
+#pragma unroll 4
+  for (int rr = 0; rr < 16; ++rr) {
+    const int row = rr * 2 + (lane >> 5);
+    const int64_t r = int64_t(bi) * kLeaf + row, c = int64_t(bj) * kLeaf + col;
+    T hi, lo;
+    encode_half<P>((r < n && c < n) ? scaled(a, lda, r, c, sc) : 0.0, hi, lo);
+    tile[row * kLeaf + col] = hi;
+    tile[half_part(1) + col * kLeaf + row] = hi;
+    if (is_split(P)) {
+      tile[half_part(2) + row * kLeaf + col] = lo;
+      tile[half_part(3) + col * kLeaf + row] = lo;
+    }
+    if (bi == bj && row == col) tr += decode_half<P>(hi, lo);
+  }
+  if (trace_part != nullptr && bi == bj) {
+    tr = wave_sum(tr);
+    if (lane == 0) trace_part[bi] = tr;
+  }
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_to_dense_half(const void* __restrict__ pool_v,
+                                                       const int32_t* __restrict__ map, int nb,
+                                                       int64_t n, int nbr, double* __restrict__ out,
+                                                       int64_t ld) {
+  typedef typename Half<P>::T T;
+  const int lane = threadIdx.x & 63;
+  const int64_t blk = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (blk >= int64_t(nbr) * nbr) return;
+  const int bi = int(blk / nbr), bj = int(blk % nbr);
+  const int32_t slot = map[int64_t(bi) * nb + bj];
+  const T* tile =
+      slot >= 0 ? static_cast<const T*>(pool_v) + int64_t(slot) * (is_split(P) ? 4 : 2) * kLeaf2
+                : nullptr;
+  const int col = lane & 31;
+#pragma unroll 4
+  for (int rr = 0; rr < 16; ++rr) {
+    const int row = rr * 2 + (lane >> 5);
+    const int64_t r = int64_t(bi) * kLeaf + row, c = int64_t(bj) * kLeaf + col;
+    if (r < n && c < n)
+      out[r * ld + c] =
+          tile ? decode_half<P>(tile[row * kLeaf + col],
+                                is_split(P) ? tile[half_part(2) + row * kLeaf + col] : T(0.0f))
+               : 0.0;
   }
 }
 
@@ -233,6 +306,7 @@ __global__ void k_init_scale(Scale* s) {
   s->eps_max = 0.0;
   s->max_abs = 0.0;
   s->max_asym = 0.0;
+  s->max_val = 0.0;
   s->nonfinite = 0;
   s->bad_bounds = 0;
 }
@@ -332,6 +406,26 @@ void launch_write_tiles(const double* a, int64_t lda, const spamm_matrix* m, con
                         double* trace_part, hipStream_t s) {
   if (m->n_blocks == 0) return;
   const unsigned g = grid_for(m->n_blocks, 4);
+  switch (m->prec) {
+    case SPAMM_BF16:
+      k_write_tiles_half<SPAMM_BF16><<<g, 256, 0, s>>>(a, lda, m->n, m->n_blocks, m->coords, m->pool,
+                                                       scale, trace_part);
+      return;
+    case SPAMM_FP16:
+      k_write_tiles_half<SPAMM_FP16><<<g, 256, 0, s>>>(a, lda, m->n, m->n_blocks, m->coords, m->pool,
+                                                       scale, trace_part);
+      return;
+    case SPAMM_BF16X3:
+      k_write_tiles_half<SPAMM_BF16X3><<<g, 256, 0, s>>>(a, lda, m->n, m->n_blocks, m->coords,
+                                                         m->pool, scale, trace_part);
+      return;
+    case SPAMM_FP16X3:
+      k_write_tiles_half<SPAMM_FP16X3><<<g, 256, 0, s>>>(a, lda, m->n, m->n_blocks, m->coords,
+                                                         m->pool, scale, trace_part);
+      return;
+    default:
+      break;
+  }
   if (m->prec == SPAMM_FP64)
     k_write_tiles<double><<<g, 256, 0, s>>>(a, lda, m->n, m->n_blocks, m->coords,
                                             static_cast<double*>(m->pool), scale, trace_part);
@@ -365,6 +459,22 @@ void launch_to_dense(const spamm_matrix* m, double* out, int64_t ld, hipStream_t
   PhaseTimer timer(SPAMM_PHASE_DENSE, s);
   const int nbr = int((m->n + kLeaf - 1) / kLeaf);
   const unsigned g = grid_for(int64_t(nbr) * nbr, 4);
+  switch (m->prec) {
+    case SPAMM_BF16:
+      k_to_dense_half<SPAMM_BF16><<<g, 256, 0, s>>>(m->pool, m->map, m->nb, m->n, nbr, out, ld);
+      return;
+    case SPAMM_FP16:
+      k_to_dense_half<SPAMM_FP16><<<g, 256, 0, s>>>(m->pool, m->map, m->nb, m->n, nbr, out, ld);
+      return;
+    case SPAMM_BF16X3:
+      k_to_dense_half<SPAMM_BF16X3><<<g, 256, 0, s>>>(m->pool, m->map, m->nb, m->n, nbr, out, ld);
+      return;
+    case SPAMM_FP16X3:
+      k_to_dense_half<SPAMM_FP16X3><<<g, 256, 0, s>>>(m->pool, m->map, m->nb, m->n, nbr, out, ld);
+      return;
+    default:
+      break;
+  }
   if (m->prec == SPAMM_FP64)
     k_to_dense<double><<<g, 256, 0, s>>>(static_cast<const double*>(m->pool), m->map, m->nb,
                                          m->n, nbr, out, ld);

@@ -56,7 +56,7 @@ def test_sp2_options_defaults_come_from_the_library():
     o = _lib.Sp2Options()
     _lib.load().sp2_options_default(ctypes.byref(o))
     assert (o.precision, o.max_iter, o.min_iter, o.stall_rule) == (1, 100, 0, 1)
-    assert o.tol == 1e-8 and o.stall_floor == 1e-3
+    assert o.tol == 1e-8 and o.stall_floor == 0.0
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):

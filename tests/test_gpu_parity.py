@@ -384,3 +384,92 @@ def test_leaf_kernels_agree_bitwise(torch_dev, lib, prec, monkeypatch):
         assert out[kern][1] == ref[1]
         np.testing.assert_array_equal(out[kern][2], ref[2])
         assert out[kern][3] == ref[3]
+
+
+# ---- 16-bit forms ----------------------------------------------------------------
+#
+# Tolerances follow the unit roundoff u of each form: BF16 u = 2^-8, FP16
+# u = 2^-11, BF16X3 (hi + lo) u ~ 2^-16, FP16X3 u ~ 2^-22, with FP32
+# accumulation (2^-24 per addition) on top.  A product's relative Frobenius
+# error is a few u (inputs rounded once each, errors averaging over the 32 k
+# of a leaf and over the k of a block): held to 2.5u, 4u, 3u and 8u.
+
+HALF_TOL = {"bf16": 1e-2, "fp16": 2e-3, "bf16x3": 5e-5, "fp16x3": 2e-6}
+
+
+def round_bf16(x):
+    f = np.asarray(x, np.float64).astype(np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return b.view(np.float32).astype(np.float64)
+
+
+def round_fp16(x):
+    return np.asarray(x, np.float64).astype(np.float32).astype(np.float16).astype(np.float64)
+
+
+@pytest.mark.parametrize("n", [20, 300])
+def test_half_tiles_roundtrip(torch_dev, lib, n):
+    a = syn.decaying(n, seed=31 + n, rate=0.03)
+    np.testing.assert_array_equal(lib.spamm_to_dense(lib.spamm_tree_build(to_dev(torch_dev, a), "bf16")),
+                                  round_bf16(a))
+    # FP16: rounded to nearest (directly or through FP32, which may differ in
+    # the last bit): within half an FP16 unit in the last place, plus a hair.
+    d = lib.spamm_to_dense(lib.spamm_tree_build(to_dev(torch_dev, a), "fp16"))
+    ulp = np.spacing(np.abs(round_fp16(a)).astype(np.float16)).astype(np.float64)
+    assert np.all(np.abs(d - a) <= 0.5 * ulp * (1 + 2.0 ** -9))
+    assert np.mean(d == round_fp16(a)) > 0.999
+    # Split forms: hi + lo reproduces the value to the hi + lo precision.
+    d = lib.spamm_to_dense(lib.spamm_tree_build(to_dev(torch_dev, a), "bf16x3"))
+    assert np.all(np.abs(d - a) <= 2.0 ** -16 * np.abs(a) + 1e-38)
+    d = lib.spamm_to_dense(lib.spamm_tree_build(to_dev(torch_dev, a), "fp16x3"))
+    assert np.all(np.abs(d - a) <= 2.0 ** -21 * np.abs(a) + 2.0 ** -24 * 2.0 ** -11)
+    # Norms stay those of the FP64 input.
+    for g, o in zip(lib.spamm_matrix_norms(lib.spamm_tree_build(to_dev(torch_dev, a), "bf16")),
+                    so.tier_norms(so.leaf_norms(so.pad(a)))):
+        np.testing.assert_allclose(g, o, rtol=1e-13)
+
+
+@pytest.mark.parametrize("prec", list(HALF_TOL))
+@pytest.mark.parametrize("n,tau", [(20, 0.0), (300, 1e-3), (700, 1e-2)])
+def test_half_multiply_matches_oracle(torch_dev, lib, prec, n, tau):
+    a = syn.decaying(n, seed=n, rate=0.05)
+    b = syn.decaying(n, seed=n + 1, rate=0.08)
+    ma = lib.spamm_tree_build(to_dev(torch_dev, a), prec)
+    mb = lib.spamm_tree_build(to_dev(torch_dev, b), prec)
+    mc, st = lib.spamm_multiply(ma, mb, tau)
+    cref, info = so.spamm(a, b, tau)
+    assert st["n_exec"] == info["n_exec"]          # culling uses FP64 norms in every form
+    assert rel(lib.spamm_to_dense(mc), cref[:n, :n]) <= HALF_TOL[prec]
+
+
+def test_fp16_range_checks(torch_dev, lib):
+    a = np.full((64, 64), 1.0)
+    a[3, 4] = 7e4
+    with pytest.raises(lib.SpammError) as e:
+        lib.spamm_tree_build(to_dev(torch_dev, a), "fp16")
+    assert e.value.code == -1
+    big = np.full((64, 64), 100.0)                  # products reach 64 * 1e4 > 65504
+    mb = lib.spamm_tree_build(to_dev(torch_dev, big), "fp16x3")
+    with pytest.raises(lib.SpammError) as e:
+        lib.spamm_multiply(mb, mb, 0.0)
+    assert e.value.code == -2
+    mb = lib.spamm_tree_build(to_dev(torch_dev, big), "bf16")   # BF16 has FP32's range
+    c, _ = lib.spamm_multiply(mb, mb, 0.0)
+    assert np.all(lib.spamm_to_dense(c) == round_bf16(640000.0))
+
+
+SP2_HALF_TOL = {"fp16x3": 1e-5, "bf16x3": 3e-4, "fp16": 2e-2, "bf16": 1e-1}
+
+
+@pytest.mark.parametrize("prec", list(SP2_HALF_TOL))
+def test_half_sp2_against_fp64_oracle(torch_dev, lib, prec):
+    """SP2 error of each 16-bit form against the FP64 oracle at the same tau,
+    on a well-gapped matrix (gap 0.5 of the spectrum width ~ 3)."""
+    f = syn.random_symmetric_with_gap(200, 60, seed=3, gap=0.5)
+    r = sp2o.sp2(f, 60, 1e-6)
+    p, st = lib.sp2_solve(to_dev(torch_dev, f), 60, 1e-6, precision=prec)
+    p = p.cpu().numpy() if hasattr(p, "cpu") else p
+    assert st["stop"] in ("converged", "stalled")
+    assert rel(p, r.p) <= SP2_HALF_TOL[prec]
+    assert abs(np.trace(p) - 60) <= 60 * SP2_HALF_TOL[prec]
