@@ -225,6 +225,87 @@ int sp2_solve(const double* f, int64_t n, int64_t ldf, int64_t n_occ, double tau
 int sp2_initial_guess(const double* f, int64_t n, int64_t ldf, int32_t prec, void* stream,
                       spamm_matrix** x0, double* eps_min, double* eps_max);
 
+/*
+ * sp2_footprint_bytes -- device memory an SP2 solve of order n in precision
+ * prec holds at its peak, as an upper bound over the fill-in SpAMM allows:
+ * the tiles of X_n and X_{n+1} (up to 3 (ceil(n/32))^2 tiles), both trees'
+ * block maps and norm pyramids, a dense FP64 copy of F and of P, the SP2
+ * partial sums and a culling workspace sized for the dense task count.
+ * Host-only arithmetic; 0 for n < 1 or an unknown precision.
+ */
+size_t sp2_footprint_bytes(int64_t n, int32_t prec);
+
+/*
+ * ---- Serving: many SP2 solves on one device -------------------------------
+ *
+ * A server owns a worker thread and a stream (default priority) on one
+ * device.  Requests are admitted first come, first served, while the sum of
+ * sp2_footprint_bytes over the running requests and the results not yet
+ * collected fits in the budget.  Each step runs one SP2 iteration of every
+ * running request: the leaf products of all requests of one precision go to
+ * one batched launch, the occlusion passes and epilogues of the requests are
+ * queued behind it, and the step ends with one synchronisation.  Every
+ * request computes exactly what sp2_solve computes for it alone (the same
+ * kernels on the same task lists, in the same order), bit for bit.
+ */
+typedef struct spamm_server spamm_server;
+
+typedef struct spamm_server_options {
+    int32_t max_active;  /* requests iterated together, 1..1024; default 64 */
+    int32_t batch_gemm;  /* 1 (default): one leaf-product launch per precision
+                            and step; 0: one launch per request */
+    int32_t device;      /* HIP device; -1 (default): the current device */
+    int32_t reserved;
+} spamm_server_options;
+
+typedef struct spamm_server_info {
+    int64_t submitted, completed, failed;  /* requests */
+    int64_t queued, active;                /* requests now waiting / running */
+    int64_t steps;                         /* lockstep iterations run */
+    int64_t gemm_launches;                 /* leaf-product launches */
+    int64_t solve_iterations;              /* SP2 iterations of completed requests */
+    uint64_t budget_bytes, used_bytes, peak_used_bytes;
+} spamm_server_info;
+
+void spamm_server_options_default(spamm_server_options* o);
+
+/* o: NULL for the defaults.  hbm_budget_bytes > 0.  Errors: INVALID_ARG,
+ * DEVICE, OOM. */
+int spamm_server_create(size_t hbm_budget_bytes, const spamm_server_options* o,
+                        spamm_server** out);
+
+/*
+ * spamm_server_submit -- queue an SP2 solve (arguments as in sp2_solve;
+ * opt NULL for the defaults).  A host F is copied during the call; a device
+ * F is read when the request starts, so it must stay valid and unchanged
+ * until the request has finished (poll/wait no longer returns PENDING).
+ * Argument errors return at once (INVALID_ARG, or OOM when the request's
+ * footprint exceeds the whole budget); errors found in F (NONFINITE,
+ * NOT_SYMMETRIC) and device failures are the request's status at poll time.
+ * request_id: the request's id (> 0).
+ */
+int spamm_server_submit(spamm_server* s, const double* f, int64_t n, int64_t ldf, int64_t n_occ,
+                        double tau, const sp2_options* opt, uint64_t* request_id);
+
+/*
+ * spamm_server_poll -- SPAMM_PENDING while the request is queued or running.
+ * Once it has finished: copies P into p (n x n FP64, ldp >= n, host or
+ * device memory of the server's device), fills st (optional), forgets the
+ * request and releases its budget, and returns its status as sp2_solve
+ * would (SPAMM_OK, SPAMM_NOT_CONVERGED or a negative error; p untouched on
+ * an error).  spamm_server_wait blocks until the request has finished.
+ * Results held for collection count against the budget: poll finished
+ * requests to keep admission going.
+ */
+int spamm_server_poll(spamm_server* s, uint64_t id, double* p, int64_t ldp, sp2_stats* st);
+int spamm_server_wait(spamm_server* s, uint64_t id, double* p, int64_t ldp, sp2_stats* st);
+
+int spamm_server_stats(spamm_server* s, spamm_server_info* out);
+
+/* Stops the worker after its current step; requests not yet collected are
+ * discarded.  NULL-safe. */
+void spamm_server_destroy(spamm_server* s);
+
 /* Unpad and upcast a handle to a dense n x n FP64 array (host or device). */
 int spamm_to_dense(const spamm_matrix* m, double* out, int64_t ld, void* stream);
 

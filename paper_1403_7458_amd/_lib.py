@@ -71,6 +71,20 @@ class Profile(ctypes.Structure):
                 ("gemm_products", ctypes.c_int64)]
 
 
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_int32), ("batch_gemm", ctypes.c_int32),
+                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("queued", ctypes.c_int64),
+                ("active", ctypes.c_int64), ("steps", ctypes.c_int64),
+                ("gemm_launches", ctypes.c_int64), ("solve_iterations", ctypes.c_int64),
+                ("budget_bytes", ctypes.c_uint64), ("used_bytes", ctypes.c_uint64),
+                ("peak_used_bytes", ctypes.c_uint64)]
+
+
 # Exported symbols and their signatures (kept in step with include/spamm.h).
 _VP, _I64, _I32, _D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
 SIGNATURES = {
@@ -95,6 +109,19 @@ SIGNATURES = {
     "spamm_profile_enable": (ctypes.c_int, [ctypes.c_int]),
     "spamm_profile_reset": (ctypes.c_int, []),
     "spamm_profile_read": (ctypes.c_int, [ctypes.POINTER(Profile)]),
+    "sp2_footprint_bytes": (ctypes.c_size_t, [_I64, _I32]),
+    "spamm_server_options_default": (None, [ctypes.POINTER(ServerOptions)]),
+    "spamm_server_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.POINTER(ServerOptions),
+                                           ctypes.POINTER(_VP)]),
+    "spamm_server_submit": (ctypes.c_int, [_VP, _VP, _I64, _I64, _I64, _D,
+                                           ctypes.POINTER(Sp2Options),
+                                           ctypes.POINTER(ctypes.c_uint64)]),
+    "spamm_server_poll": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _I64,
+                                         ctypes.POINTER(Sp2Stats)]),
+    "spamm_server_wait": (ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _I64,
+                                         ctypes.POINTER(Sp2Stats)]),
+    "spamm_server_stats": (ctypes.c_int, [_VP, ctypes.POINTER(ServerInfo)]),
+    "spamm_server_destroy": (None, [_VP]),
 }
 
 _lock = threading.Lock()
@@ -282,8 +309,12 @@ def sp2_solve(f, n_occ: int, tau: float, out=None, stream=None, **opts):
     rc = load().sp2_solve(pf, n, ldf, int(n_occ), float(tau), ctypes.byref(o), _stream(stream), pp,
                           ldp, ctypes.byref(st))
     _check(rc, allow=(OK, NOT_CONVERGED))
+    return out, _sp2_stats(rc, st)
+
+
+def _sp2_stats(rc: int, st: Sp2Stats) -> dict:
     it = st.iterations
-    stats = {
+    return {
         "status": rc, "iterations": it, "stop": STOP_REASONS[st.stop_reason],
         "eps_min": st.eps_min, "eps_max": st.eps_max, "trace_final": st.trace_final,
         "n_exec_total": st.n_exec_total,
@@ -291,7 +322,82 @@ def sp2_solve(f, n_occ: int, tau: float, out=None, stream=None, **opts):
         "traces": list(st.trace[:it]), "errors": list(st.err[:it]),
         "n_exec": [int(x) for x in st.n_exec[:it]], "n_blocks": [int(x) for x in st.n_blocks[:it]],
     }
-    return out, stats
+
+
+def sp2_footprint_bytes(n: int, precision="fp32") -> int:
+    """Peak device memory of one SP2 solve of order n (an upper bound)."""
+    return int(load().sp2_footprint_bytes(int(n), PRECISIONS.get(precision, precision)))
+
+
+class Sp2Server:
+    """Owning wrapper of a spamm_server: SP2 requests solved together on one
+    device, one iteration of every running request per step."""
+
+    def __init__(self, budget_bytes: int, max_active: int = 64, batch_gemm: bool = True,
+                 device: int = -1):
+        lib = load()
+        o = ServerOptions()
+        lib.spamm_server_options_default(ctypes.byref(o))
+        o.max_active, o.batch_gemm, o.device = int(max_active), int(bool(batch_gemm)), int(device)
+        self._h = ctypes.c_void_p()
+        _check(lib.spamm_server_create(int(budget_bytes), ctypes.byref(o), ctypes.byref(self._h)))
+        self._inputs = {}   # device inputs, kept alive until their request finishes
+
+    def submit(self, f, n_occ: int, tau: float, **opts) -> int:
+        pf, n, ldf, keep = _dense_arg(f)
+        o = sp2_options(**opts)
+        rid = ctypes.c_uint64()
+        _check(load().spamm_server_submit(self._h, pf, n, ldf, int(n_occ), float(tau),
+                                          ctypes.byref(o), ctypes.byref(rid)))
+        self._inputs[rid.value] = (keep, n)
+        return rid.value
+
+    def _collect(self, fn, rid: int, out):
+        if rid not in self._inputs:  # unknown or already collected: the library says which
+            _check(fn(self._h, ctypes.c_uint64(rid), None, 0, None))
+        keep, n = self._inputs[rid]
+        if out is None:
+            out = np.empty((n, n), np.float64)
+        pp, n2, ldp, keep_p = _dense_arg(out)
+        if n2 != n:
+            raise ValueError("output size mismatch")
+        st = Sp2Stats()
+        rc = fn(self._h, ctypes.c_uint64(rid), pp, ldp, ctypes.byref(st))
+        if rc == PENDING:
+            return None
+        del self._inputs[rid]
+        _check(rc, allow=(OK, NOT_CONVERGED))
+        return out, _sp2_stats(rc, st)
+
+    def poll(self, rid: int, out=None):
+        """None while pending, else (P, stats) as sp2_solve returns them."""
+        return self._collect(load().spamm_server_poll, rid, out)
+
+    def wait(self, rid: int, out=None):
+        return self._collect(load().spamm_server_wait, rid, out)
+
+    def stats(self) -> dict:
+        inf = ServerInfo()
+        _check(load().spamm_server_stats(self._h, ctypes.byref(inf)))
+        return {f: int(getattr(inf, f)) for f, _ in ServerInfo._fields_}
+
+    def close(self):
+        if self._h is not None and self._h.value:
+            load().spamm_server_destroy(self._h)
+        self._h = None
+        self._inputs = {}
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def profile_enable(on: bool = True):

@@ -12,9 +12,9 @@
 
 namespace spamm {
 
-namespace {
-
 thread_local std::string g_last_error;
+
+void set_last_error(const std::string& m) { g_last_error = m; }
 
 int fail(const Error& e) {
   g_last_error = e.msg;
@@ -95,54 +95,10 @@ int current_device() {
   return d;
 }
 
-// A dense FP64 input on the device: either the caller's pointer or a
-// staged copy of host memory (owned here).
-struct DenseIn {
-  const double* p = nullptr;
-  int64_t ld = 0;
-  double* owned = nullptr;
-  hipStream_t s = nullptr;
-  Error take(const double* src, int64_t n, int64_t ld_src, hipStream_t st) {
-    s = st;
-    if (is_device_ptr(src)) {
-      p = src;
-      ld = ld_src;
-      return Error{};
-    }
-    SPAMM_TRY(dev_alloc_n(&owned, n * n, st));
-    SPAMM_HIP(hipMemcpy2DAsync(owned, size_t(n) * 8, src, size_t(ld_src) * 8, size_t(n) * 8,
-                               size_t(n), hipMemcpyHostToDevice, st));
-    p = owned;
-    ld = n;
-    return Error{};
-  }
-  ~DenseIn() {
-    if (owned) dev_free(owned, s);
-  }
-};
-
-// Per-thread reusable workspace of the culling pass, kept for the life of
-// the thread (never destroyed, so no HIP call runs from a static destructor).
-struct Workspace {
-  CullWork cull;
-  hipStream_t last = nullptr;
-  bool used = false;
-  int device = -1;
-  void bind(hipStream_t s) {
-    const int d = current_device();
-    if (device != d) {
-      if (used) cull.release(last);
-      device = d;
-    }
-    if (used && last != s) (void)hipStreamSynchronize(last);
-    last = s;
-    used = true;
-  }
-};
-thread_local Workspace* g_ws_ptr = nullptr;
 Workspace& ws() {
-  if (!g_ws_ptr) g_ws_ptr = new Workspace();
-  return *g_ws_ptr;
+  static thread_local Workspace* w = nullptr;
+  if (!w) w = new Workspace();  // never destroyed: no HIP call from static destructors
+  return *w;
 }
 
 bool valid_prec(int p) { return p >= SPAMM_FP64 && p <= SPAMM_FP16X3; }
@@ -283,8 +239,6 @@ Error multiply_impl(const spamm_matrix* a, const spamm_matrix* b, double tau, hi
   *c_out = c;
   return Error{};
 }
-
-}  // namespace
 
 // ---- shared helpers ---------------------------------------------------------
 
@@ -648,292 +602,3 @@ int spamm_profile_read(spamm_profile* out) {
 }
 
 }  // extern "C"
-
-// ---- SP2 -----------------------------------------------------------------------
-
-namespace {
-
-struct Sp2Buffers {
-  hipStream_t s = nullptr;
-  double* row = nullptr;      // 3 n: Gershgorin lo, hi, max
-  Scale* scale = nullptr;
-  int64_t* cnt = nullptr;
-  double* trace_part = nullptr;
-  double* err_part = nullptr;
-  ~Sp2Buffers() {
-    dev_free(row, s);
-    dev_free(scale, s);
-    dev_free(cnt, s);
-    dev_free(trace_part, s);
-    dev_free(err_part, s);
-  }
-};
-
-// Gershgorin bounds and input checks of F, then the tree of
-// X_0 = (eps_max I - F) / (eps_max - eps_min) (the SP2 scaling; Sec. 4):
-// leaf norms of the FP64 values of X_0, then its tiles, with the diagonal
-// sums of the stored values in buf.trace_part.
-Error sp2_ingest(const double* f, int64_t ldf, int64_t n, int prec, Sp2Buffers& buf,
-                 hipStream_t s, spamm_matrix** x, Scale* sh) {
-  int nb = 1;
-  while (int64_t(kLeaf) * nb < n) nb *= 2;
-  SPAMM_TRY(dev_alloc_n(&buf.row, 3 * n, s));
-  SPAMM_TRY(dev_alloc_n(&buf.scale, 1, s));
-  SPAMM_TRY(dev_alloc_n(&buf.cnt, 2, s));
-  SPAMM_TRY(dev_alloc_n(&buf.trace_part, nb, s));
-  {
-    PhaseTimer timer(SPAMM_PHASE_TREE, s);
-    launch_init_scale(buf.scale, s);
-    launch_gershgorin_scale(f, n, ldf, buf.row, buf.row + n, buf.row + 2 * n, buf.scale, s);
-    launch_asymmetry(f, n, ldf, buf.scale, s);
-  }
-  // Reject bad input before building anything.
-  SPAMM_TRY(read_small(sh, buf.scale, sizeof(Scale), s));
-  if (sh->nonfinite) return err(SPAMM_ERR_NONFINITE, "F holds NaN or Inf");
-  if (sh->max_asym > 1e-12 * sh->max_abs)
-    return err(SPAMM_ERR_NOT_SYMMETRIC, "F is not symmetric (max|F - F^T| > 1e-12 max|F|)");
-  if (sh->bad_bounds)
-    return err(SPAMM_ERR_INVALID_ARG, "degenerate spectrum bounds (eps_max <= eps_min)");
-  return build_from_dense(f, ldf, n, prec, buf.scale, buf.trace_part, s, x, sh, buf.cnt);
-}
-
-Error sp2_impl(const double* f, int64_t n, int64_t ldf, int64_t n_occ, double tau,
-               const sp2_options* opt_in, hipStream_t s, double* p, int64_t ldp, sp2_stats* st,
-               int* status) {
-  sp2_options opt;
-  sp2_options_default(&opt);
-  if (opt_in) opt = *opt_in;
-  if (!f || !p) return err(SPAMM_ERR_INVALID_ARG, "NULL pointer");
-  if (n < 1 || ldf < n || ldp < n) return err(SPAMM_ERR_INVALID_ARG, "need n >= 1, ldf >= n, ldp >= n");
-  if (n_occ < 0 || n_occ > n) return err(SPAMM_ERR_INVALID_ARG, "need 0 <= n_occ <= n");
-  SPAMM_TRY(check_tau(tau));
-  if (!valid_prec(opt.precision)) return err(SPAMM_ERR_INVALID_ARG, "unsupported precision");
-  if (opt.max_iter < 1 || opt.max_iter > SP2_MAX_ITER || opt.min_iter < 0 ||
-      !(opt.tol >= 0.0) || !(opt.stall_floor >= 0.0))
-    return err(SPAMM_ERR_INVALID_ARG, "bad sp2 options");
-  ws().bind(s);
-  CullWork& w = ws().cull;
-  SPAMM_TRY(ensure_control(w));
-  DenseIn in;
-  SPAMM_TRY(in.take(f, n, ldf, s));
-  Sp2Buffers buf;
-  buf.s = s;
-  Scale sh;
-  spamm_matrix* x = nullptr;
-  SPAMM_TRY(sp2_ingest(in.p, in.ld, n, opt.precision, buf, s, &x, &sh));
-  const int64_t cells = int64_t(x->nb) * x->nb;
-  Error e0 = dev_alloc_n(&buf.err_part, cells, s);
-  if (!e0.ok()) {
-    free_matrix(x);
-    return e0;
-  }
-  const int nb = x->nb;
-  Control* ctl = w.ctl_dev;
-  launch_sp2_reduce(nb, buf.trace_part, nullptr, nullptr, ctl, s);
-  if (st) {
-    std::memset(st, 0, sizeof(*st));
-    st->eps_min = sh.eps_min;
-    st->eps_max = sh.eps_max;
-  }
-  CullResult cr;
-  Error e = run_cull(w, x, x, tau, false, s, &cr);
-  if (!e.ok()) {
-    free_matrix(x);
-    return e;
-  }
-  double t_n = w.ctl_host->sp2_trace;
-  std::vector<double> errs;
-  // The stall rule acts below stall_floor * ||P||_F, ||P||_F = sqrt(n_occ);
-  // stall_floor = 0 picks max(1e-3, 4 u) for the leaf precision's unit
-  // roundoff u, since the floor of e_n grows with u.
-  double floor_rel = opt.stall_floor;
-  if (floor_rel == 0.0) {
-    static const double unit[] = {0x1p-53, 0x1p-24, 0x1p-8, 0x1p-11, 0x1p-16, 0x1p-22};
-    floor_rel = std::max(1e-3, 4.0 * unit[opt.precision]);
-  }
-  const double stall_at = floor_rel * std::sqrt(double(std::max<int64_t>(n_occ, 1)));
-  int stop = SP2_STOP_MAX_ITER;
-  int it = 0;
-  int64_t total_exec = 0;
-  for (it = 0; it < opt.max_iter; ++it) {
-    const bool square = t_n > double(n_occ);
-    spamm_matrix* y = nullptr;
-    e = new_matrix(n, opt.precision, s, &y);
-    if (e.ok()) e = alloc_pool(y, std::max<int64_t>(cr.n_cblocks + (square ? 0 : x->n_blocks), 1), s);
-    if (!e.ok()) {
-      free_matrix(y);
-      free_matrix(x);
-      return e;
-    }
-    launch_sp2_prepare(y->map, y->norms + tier_offset(y->depth), buf.err_part, nb,
-                       buf.trace_part, &ctl->scratch[1], s);
-    GemmArgs g{};
-    g.nb = nb;
-    g.n_nodes = cr.n_cblocks;
-    g.nodes = cr.nodes;
-    g.nptr = cr.nptr;
-    g.ks = cr.ks;
-    g.n_super = cr.n_super;
-    g.sup_nodes = cr.sup_nodes;
-    g.sup_nptr = cr.sup_nptr;
-    g.sup_ks = cr.sup_ks;
-    g.sup_bits = cr.sup_bits;
-    g.sup_cnt4 = cr.sup_cnt4;
-    g.sup_noff = cr.sup_noff;
-    if (opt.precision == SPAMM_FP32 && cr.n_quad > 0 && leaf_kernel_choice() == kLeaf4x4) {
-      launch_quad_masks(cr, x, x, tau, s);
-      launch_scatter_nodes(cr.nodes, cr.n_cblocks, nb, y->map, y->coords, s);
-      g.n_quad = cr.n_quad;
-      g.quad_nodes = cr.quad_nodes;
-      g.quad_nptr = cr.quad_nptr;
-      g.quad_ks = cr.quad_ks;
-      g.quad_masks = cr.quad_masks;
-    }
-    g.pool_a = x->pool;
-    g.map_a = x->map;
-    g.pool_b = x->pool;
-    g.map_b = x->map;
-    g.pool_c = y->pool;
-    g.map_c = y->map;
-    g.coords_c = y->coords;
-    g.norm_c = y->norms + tier_offset(y->depth);
-    g.sp2 = 1;
-    g.square = square ? 1 : 0;
-    g.pool_x = x->pool;
-    g.map_x = x->map;
-    g.trace_part = buf.trace_part;
-    g.err_part = buf.err_part;
-    g.overflow = reinterpret_cast<int32_t*>(&ctl->scratch[2]);
-    {
-      PhaseTimer timer(SPAMM_PHASE_GEMM, s, cr.n_tasks);
-      launch_leaf_gemm(opt.precision, g, s);
-    }
-    {
-      PhaseTimer timer(SPAMM_PHASE_EPILOGUE, s);
-      RestArgs r{};
-      r.nb = nb;
-      r.square = g.square;
-      r.n_x = x->n_blocks;
-      r.pool_x = x->pool;
-      r.coords_x = x->coords;
-      r.base_slot = cr.n_cblocks;
-      r.pool_out = y->pool;
-      r.map_out = y->map;
-      r.coords_out = y->coords;
-      r.norm_out = y->norms + tier_offset(y->depth);
-      r.trace_part = buf.trace_part;
-      r.err_part = buf.err_part;
-      r.counter = &ctl->scratch[1];
-      launch_sp2_rest(opt.precision, r, s);
-      launch_sp2_reduce(nb, buf.trace_part, buf.err_part, nullptr, ctl, s);
-    }
-    launch_pyramid(y, s);
-    const int64_t n_exec = cr.n_tasks, y_direct = cr.n_cblocks;
-    total_exec += n_exec;
-    if (st) {
-      st->branch[it] = square ? 1 : 0;
-      st->trace[it] = t_n;
-      st->n_exec[it] = n_exec;
-      st->n_blocks[it] = x->n_blocks;
-    }
-    // The next product's occlusion pass is queued before the one
-    // synchronisation of this iteration, which also brings back t_{n+1}
-    // and e_n.
-    if (it + 1 < opt.max_iter) {
-      e = run_cull(w, y, y, tau, false, s, &cr);
-    } else {
-      e = read_small(w.ctl_host, ctl, sizeof(Control), s);
-    }
-    if (!e.ok()) {
-      free_matrix(y);
-      free_matrix(x);
-      return e;
-    }
-    if (w.ctl_host->scratch[2] != 0) {
-      free_matrix(y);
-      free_matrix(x);
-      return err(SPAMM_ERR_NONFINITE, "SP2 iterate is not finite or leaves FP16's range");
-    }
-    const double e_n = std::sqrt(w.ctl_host->sp2_err2);
-    t_n = w.ctl_host->sp2_trace;
-    y->n_blocks = y_direct + w.ctl_host->extra_blocks;
-    errs.push_back(e_n);
-    if (st) st->err[it] = e_n;
-    free_matrix(x);
-    x = y;
-    if (it + 1 >= opt.min_iter) {
-      if (e_n < opt.tol) {
-        stop = SP2_STOP_CONVERGED;
-        break;
-      }
-      if (opt.stall_rule && it >= 2 && e_n < stall_at && e_n >= errs[it - 2]) {
-        stop = SP2_STOP_STALLED;
-        break;
-      }
-    }
-  }
-  const int iters = std::min(it + 1, opt.max_iter);
-  if (st) {
-    st->iterations = iters;
-    st->stop_reason = stop;
-    st->trace_final = t_n;
-    st->n_exec_total = total_exec;
-  }
-  // P = X_{n+1} of the stopping iteration, unpadded to FP64.
-  if (is_device_ptr(p)) {
-    launch_to_dense(x, p, ldp, s);
-    hipError_t h = hipStreamSynchronize(s);
-    free_matrix(x);
-    if (h != hipSuccess) return hip_error(h, "hipStreamSynchronize");
-  } else {
-    double* tmp = nullptr;
-    e = dev_alloc_n(&tmp, n * n, s);
-    if (!e.ok()) {
-      free_matrix(x);
-      return e;
-    }
-    launch_to_dense(x, tmp, n, s);
-    hipError_t h = hipMemcpy2DAsync(p, size_t(ldp) * 8, tmp, size_t(n) * 8, size_t(n) * 8,
-                                    size_t(n), hipMemcpyDeviceToHost, s);
-    if (h == hipSuccess) h = hipStreamSynchronize(s);
-    dev_free(tmp, s);
-    free_matrix(x);
-    if (h != hipSuccess) return hip_error(h, "hipMemcpy2DAsync");
-  }
-  *status = stop == SP2_STOP_MAX_ITER ? SPAMM_NOT_CONVERGED : SPAMM_OK;
-  return Error{};
-}
-
-}  // namespace
-
-extern "C" int sp2_solve(const double* f, int64_t n, int64_t ldf, int64_t n_occ, double tau,
-                         const sp2_options* opt, void* stream, double* p, int64_t ldp,
-                         sp2_stats* st) {
-  int status = SPAMM_OK;
-  Error e = sp2_impl(f, n, ldf, n_occ, tau, opt, static_cast<hipStream_t>(stream), p, ldp, st,
-                     &status);
-  if (!e.ok()) return fail(e);
-  if (status == SPAMM_NOT_CONVERGED) g_last_error = "SP2 reached max_iter without converging";
-  return status;
-}
-
-extern "C" int sp2_initial_guess(const double* f, int64_t n, int64_t ldf, int32_t prec,
-                                 void* stream, spamm_matrix** x0, double* eps_min,
-                                 double* eps_max) {
-  if (x0) *x0 = nullptr;
-  if (!f || !x0) return fail(SPAMM_ERR_INVALID_ARG, "NULL pointer");
-  if (n < 1 || ldf < n) return fail(SPAMM_ERR_INVALID_ARG, "need n >= 1 and ldf >= n");
-  if (!valid_prec(prec)) return fail(SPAMM_ERR_INVALID_ARG, "unsupported precision");
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  DenseIn in;
-  Error e = in.take(f, n, ldf, s);
-  if (!e.ok()) return fail(e);
-  Sp2Buffers buf;
-  buf.s = s;
-  Scale sh;
-  e = sp2_ingest(in.p, in.ld, n, prec, buf, s, x0, &sh);
-  if (!e.ok()) return fail(e);
-  if (eps_min) *eps_min = sh.eps_min;
-  if (eps_max) *eps_max = sh.eps_max;
-  return SPAMM_OK;
-}

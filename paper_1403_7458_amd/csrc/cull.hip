@@ -618,8 +618,8 @@ CullWork::~CullWork() {
   if (ctl_host) (void)hipHostFree(ctl_host);
 }
 
-Error run_cull(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
-               bool want_pairs, hipStream_t s, CullResult* out) {
+Error cull_launch(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
+                  bool want_pairs, hipStream_t s) {
   const int d = a->depth;
   const int t_top = std::min(d, kTopTier);
   SPAMM_TRY(ensure_control(w));
@@ -640,7 +640,6 @@ Error run_cull(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double
   for (int t = 0; t <= d; ++t) SPAMM_TRY(reserve_tier(w, t, s));
   SPAMM_TRY(w.part.reserve(3 * kParts * sizeof(int64_t), s));
   Control* ctl = w.ctl_dev;
-  out->restarts = 0;
   {
     PhaseTimer timer(SPAMM_PHASE_CULL, s);
     launch_top(w, a, b, t_top, tau, s);
@@ -649,9 +648,20 @@ Error run_cull(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double
       k_nonzero_pairs<<<1, 1024, 0, s>>>(a->norms + tier_offset(d), b->norms + tier_offset(d),
                                          a->nb, ctl);
   }
-  for (;;) {
-    SPAMM_HIP(hipMemcpyAsync(w.ctl_host, ctl, sizeof(Control), hipMemcpyDeviceToHost, s));
-    SPAMM_HIP(hipStreamSynchronize(s));
+  SPAMM_HIP(hipMemcpyAsync(w.ctl_host, ctl, sizeof(Control), hipMemcpyDeviceToHost, s));
+  return Error{};
+}
+
+Error cull_finish(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
+                  bool want_pairs, hipStream_t s, CullResult* out) {
+  const int d = a->depth;
+  Control* ctl = w.ctl_dev;
+  out->restarts = 0;
+  for (bool first = true;; first = false) {
+    if (!first) {
+      SPAMM_HIP(hipMemcpyAsync(w.ctl_host, ctl, sizeof(Control), hipMemcpyDeviceToHost, s));
+      SPAMM_HIP(hipStreamSynchronize(s));
+    }
     const Control& h = *w.ctl_host;
     int bad = -1;
     for (int t = 1; t <= d; ++t)
@@ -721,6 +731,13 @@ void launch_scatter_nodes(const int32_t* nodes, int64_t n, int nb, int32_t* map_
                           int32_t* coords_c, hipStream_t s) {
   if (n <= 0) return;
   k_scatter_nodes<<<unsigned((n + 255) / 256), 256, 0, s>>>(nodes, n, nb, map_c, coords_c);
+}
+
+Error run_cull(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
+               bool want_pairs, hipStream_t s, CullResult* out) {
+  SPAMM_TRY(cull_launch(w, a, b, tau, want_pairs, s));
+  SPAMM_HIP(hipStreamSynchronize(s));
+  return cull_finish(w, a, b, tau, want_pairs, s, out);
 }
 
 }  // namespace spamm

@@ -226,6 +226,13 @@ struct CullResult {
 // non-zero block pairs is computed too.
 Error run_cull(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
                bool want_pairs, hipStream_t s, CullResult* out);
+// The same in two halves: cull_launch queues the pass and the copy of the
+// control block to w.ctl_host; after the caller has synchronised `s`,
+// cull_finish regrows and resumes where needed and fills `out`.
+Error cull_launch(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
+                  bool want_pairs, hipStream_t s);
+Error cull_finish(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
+                  bool want_pairs, hipStream_t s, CullResult* out);
 Error ensure_control(CullWork& w);
 // The 64-bit leaf masks of the tier d-2 frontier (see CullResult).  Each bit
 // repeats the decisions the tier walk took for that leaf product and its
@@ -292,6 +299,60 @@ void launch_leaf_gemm(int prec, const GemmArgs& g, hipStream_t s);
 // 16-bit forms (leafgemm16.hip).
 void launch_leaf_gemm_half(int prec, const GemmArgs& g, hipStream_t s);
 
+// Batched launch: the leaf products of several independent products of one
+// precision in one grid.  Waves are numbered across the products in the
+// order of job[]; product job[r] owns waves [first[r], first[r + 1]) and
+// each wave runs exactly the work its index selects in a launch of that
+// product alone, so the results are bitwise those of separate launches.
+constexpr int kMaxBatch = 64;
+struct GemmBatch {
+  const GemmArgs* args;            // device array
+  int32_t n;
+  int32_t job[kMaxBatch];
+  int64_t first[kMaxBatch + 1];
+};
+// The product of wave `item` (rebased to that product), or NULL past the end.
+__device__ inline const GemmArgs* batch_locate(const GemmBatch& b, int64_t& item) {
+  if (item >= b.first[b.n]) return nullptr;
+  int lo = 0, hi = b.n - 1;  // largest r with first[r] <= item
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (b.first[mid] <= item)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  item -= b.first[lo];
+  return b.args + b.job[lo];
+}
+// host[r] and dev[r] hold the same arguments, on the host and the device;
+// every product is of precision prec.  Products whose kernel has no batched
+// form (the LDS-staged FP32 variants) are launched one by one.
+void launch_leaf_gemm_batch(int prec, const GemmArgs* host, const GemmArgs* dev, int n,
+                            hipStream_t s);
+void launch_leaf_gemm_half_batch(int prec, const GemmArgs* host, const GemmArgs* dev, int n,
+                                 hipStream_t s);
+// Fills groups of at most kMaxBatch products of one kind: items(r) is the
+// number of waves product r needs (0: skipped); emit(batch) launches.
+template <class Items, class Emit>
+void for_each_batch(const GemmArgs* dev, int n, Items items, Emit emit) {
+  GemmBatch b{};
+  b.args = dev;
+  b.n = 0;
+  b.first[0] = 0;
+  for (int r = 0; r < n; ++r) {
+    const int64_t w = items(r);
+    if (w <= 0) continue;
+    b.job[b.n] = r;
+    b.first[b.n + 1] = b.first[b.n] + w;
+    if (++b.n == kMaxBatch) {
+      emit(b);
+      b.n = 0;
+    }
+  }
+  if (b.n > 0) emit(b);
+}
+
 // SP2: blocks of X_n without any executed product.
 struct RestArgs {
   int nb;
@@ -318,5 +379,71 @@ void launch_sp2_prepare(int32_t* map, double* norm_leaf, double* err_part, int n
 // norms into ctl->sp2_trace, sp2_err2, frob2.
 void launch_sp2_reduce(int nb, const double* trace_part, const double* err_part,
                        const double* norm_leaf, Control* ctl, hipStream_t s);
+
+// ---- api.hip: host helpers shared by the C ABI's translation units ----------
+
+Error err(int code, const std::string& msg);
+int fail(const Error& e);                       // records e.msg, returns e.code
+int fail(int code, const std::string& msg);
+void set_last_error(const std::string& m);      // this thread's spamm_last_error()
+// Small device-to-host read through pinned staging; synchronises s.
+Error read_small(void* host, const void* dev, size_t bytes, hipStream_t s);
+bool is_device_ptr(const void* p);              // device memory (else host memory)
+int current_device();
+bool valid_prec(int p);
+Error check_tau(double tau);
+
+// A dense FP64 input on the device: either the caller's pointer or a
+// staged copy of host memory (owned here).
+struct DenseIn {
+  const double* p = nullptr;
+  int64_t ld = 0;
+  double* owned = nullptr;
+  hipStream_t s = nullptr;
+  Error take(const double* src, int64_t n, int64_t ld_src, hipStream_t st) {
+    s = st;
+    if (is_device_ptr(src)) {
+      p = src;
+      ld = ld_src;
+      return Error{};
+    }
+    SPAMM_TRY(dev_alloc_n(&owned, n * n, st));
+    SPAMM_HIP(hipMemcpy2DAsync(owned, size_t(n) * 8, src, size_t(ld_src) * 8, size_t(n) * 8,
+                               size_t(n), hipMemcpyHostToDevice, st));
+    p = owned;
+    ld = n;
+    return Error{};
+  }
+  ~DenseIn() {
+    if (owned) dev_free(owned, s);
+  }
+};
+
+// Per-thread reusable workspace of the culling pass, kept for the life of
+// the thread (never destroyed, so no HIP call runs from a static destructor).
+struct Workspace {
+  CullWork cull;
+  hipStream_t last = nullptr;
+  bool used = false;
+  int device = -1;
+  void bind(hipStream_t s) {
+    const int d = current_device();
+    if (device != d) {
+      if (used) cull.release(last);
+      device = d;
+    }
+    if (used && last != s) (void)hipStreamSynchronize(last);
+    last = s;
+    used = true;
+  }
+};
+Workspace& ws();  // this thread's, kept for the life of the thread
+
+// Tree of a dense FP64 device matrix under `scale` (leaf norms, compaction,
+// tiles, pyramid); the Scale read back into *scale_host.  With trace_part
+// the diagonal-block sums of the stored values land there.
+Error build_from_dense(const double* a_dev, int64_t lda, int64_t n, int prec, Scale* scale,
+                       double* trace_part, hipStream_t s, spamm_matrix** out, Scale* scale_host,
+                       int64_t* count_dev);
 
 }  // namespace spamm

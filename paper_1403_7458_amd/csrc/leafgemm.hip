@@ -132,10 +132,10 @@ __device__ inline void mma_f32(const F32Frag& f, v16f& acc) {
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(f.a[s >> 2][s & 3], f.b[s], acc, 0, 0, 0);
 }
 
-__global__ void __launch_bounds__(256) k_leaf_gemm_f32(GemmArgs g) {
-  const int lane = threadIdx.x & 63;
-  const int64_t node = uniform(xcd_contiguous_block() * kWaves + (threadIdx.x >> 6));
-  if (node >= g.n_nodes) return;
+// One wave per C block over its leaf task list; slots: the wave's [128]
+// LDS table.
+__device__ __forceinline__ void f32_block(const GemmArgs& g, int64_t node, int lane,
+                                          int32_t* slots) {
   const int32_t ij = uniform(g.nodes[node]);
   const int i = unpack_i(ij), j = unpack_j(ij);
   const float* pa = static_cast<const float*>(g.pool_a);
@@ -143,8 +143,7 @@ __global__ void __launch_bounds__(256) k_leaf_gemm_f32(GemmArgs g) {
   const int64_t t0 = uniform(g.nptr[node]), t1 = uniform(g.nptr[node + 1]);
   v16f acc = {};
   F32Frag cur, nxt;
-  __shared__ int32_t s_slots[kWaves][128];
-  TaskSlots ts(g, i, j, t0, t1, s_slots[threadIdx.x >> 6], lane);
+  TaskSlots ts(g, i, j, t0, t1, slots, lane);
   if (t0 < t1) {
     // Two operand sets in alternation: the next product's loads are always
     // in flight while the current product runs on the MFMA unit.  The loop
@@ -188,6 +187,21 @@ __global__ void __launch_bounds__(256) k_leaf_gemm_f32(GemmArgs g) {
     out[row * kLeaf + col] = e.apply(acc[r], x, g.sp2, g.square, i == j && row == col);
   }
   e.finish(g, node, ij, lane);
+}
+
+__global__ void __launch_bounds__(256) k_leaf_gemm_f32(GemmArgs g) {
+  __shared__ int32_t s_slots[kWaves][128];
+  const int64_t node = uniform(xcd_contiguous_block() * kWaves + (threadIdx.x >> 6));
+  if (node >= g.n_nodes) return;
+  f32_block(g, node, threadIdx.x & 63, s_slots[threadIdx.x >> 6]);
+}
+
+__global__ void __launch_bounds__(256) k_leaf_gemm_f32_batch(GemmBatch b) {
+  __shared__ int32_t s_slots[kWaves][128];
+  int64_t node = uniform(xcd_contiguous_block() * kWaves + (threadIdx.x >> 6));
+  const GemmArgs* g = batch_locate(b, node);
+  if (!g) return;
+  f32_block(*g, node, threadIdx.x & 63, s_slots[threadIdx.x >> 6]);
 }
 
 // ---- FP32 leaf products on 2 x 2 groups of C blocks --------------------------
@@ -381,13 +395,10 @@ constexpr int kWBatch = 32;            // list entries per slot batch (64 steps)
 
 // kAhead: operand sets in flight per wave (2: the next step's loads overlap
 // the current step's products; 1: other waves hide the latency).
+// Group p of g; tab: the wave's LDS step table (mask, 4 slots per step).
 template <int kAhead>
-__global__ void __launch_bounds__(256) k_leaf_gemm_f32_w2x2(GemmArgs g) {
-  __shared__ int32_t s_tab[kWaves][5][2 * kWBatch];  // mask, 4 slots per step
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t p = uniform(xcd_contiguous_block() * kWaves + wave);
-  if (p >= g.n_super) return;
-  int32_t(*tab)[2 * kWBatch] = s_tab[wave];
+__device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
+                                         int32_t (*tab)[2 * kWBatch]) {
   const int32_t IJ = uniform(g.sup_nodes[p]);
   const int I = unpack_i(IJ), J = unpack_j(IJ);
   const float* pa = static_cast<const float*>(g.pool_a);
@@ -488,6 +499,25 @@ __global__ void __launch_bounds__(256) k_leaf_gemm_f32_w2x2(GemmArgs g) {
   emit(1, acc[1]);
   emit(2, acc[2]);
   emit(3, acc[3]);
+}
+
+template <int kAhead>
+__global__ void __launch_bounds__(256) k_leaf_gemm_f32_w2x2(GemmArgs g) {
+  __shared__ int32_t s_tab[kWaves][5][2 * kWBatch];
+  const int wave = threadIdx.x >> 6;
+  const int64_t p = uniform(xcd_contiguous_block() * kWaves + wave);
+  if (p >= g.n_super) return;
+  f32_w2x2<kAhead>(g, p, threadIdx.x & 63, s_tab[wave]);
+}
+
+template <int kAhead>
+__global__ void __launch_bounds__(256) k_leaf_gemm_f32_w2x2_batch(GemmBatch b) {
+  __shared__ int32_t s_tab[kWaves][5][2 * kWBatch];
+  const int wave = threadIdx.x >> 6;
+  int64_t p = uniform(xcd_contiguous_block() * kWaves + wave);
+  const GemmArgs* g = batch_locate(b, p);
+  if (!g) return;
+  f32_w2x2<kAhead>(*g, p, threadIdx.x & 63, s_tab[wave]);
 }
 
 // ---- FP32 leaf products on 4 x 4 groups of C blocks --------------------------
@@ -672,10 +702,8 @@ __device__ inline void mma_f64(const F64Frag& f, v4d (&acc)[2][2]) {
         acc[p][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.a[p][s], f.b[q][s], acc[p][q], 0, 0, 0);
 }
 
-__global__ void __launch_bounds__(256) k_leaf_gemm_f64(GemmArgs g) {
-  const int lane = threadIdx.x & 63;
-  const int64_t node = uniform(xcd_contiguous_block() * kWaves + (threadIdx.x >> 6));
-  if (node >= g.n_nodes) return;
+__device__ __forceinline__ void f64_block(const GemmArgs& g, int64_t node, int lane,
+                                          int32_t* slots) {
   const int32_t ij = uniform(g.nodes[node]);
   const int i = unpack_i(ij), j = unpack_j(ij);
   const double* pa = static_cast<const double*>(g.pool_a);
@@ -683,8 +711,7 @@ __global__ void __launch_bounds__(256) k_leaf_gemm_f64(GemmArgs g) {
   const int64_t t0 = uniform(g.nptr[node]), t1 = uniform(g.nptr[node + 1]);
   v4d acc[2][2] = {};
   F64Frag cur, nxt;
-  __shared__ int32_t s_slots[kWaves][128];
-  TaskSlots ts(g, i, j, t0, t1, s_slots[threadIdx.x >> 6], lane);
+  TaskSlots ts(g, i, j, t0, t1, slots, lane);
   if (t0 < t1) {
     // Two operand sets in alternation: the next product's loads are always
     // in flight while the current product runs on the MFMA unit.  The loop
@@ -732,6 +759,21 @@ __global__ void __launch_bounds__(256) k_leaf_gemm_f64(GemmArgs g) {
         out[row * kLeaf + col] = e.apply(acc[p][q][r], x, g.sp2, g.square, i == j && row == col);
       }
   e.finish(g, node, ij, lane);
+}
+
+__global__ void __launch_bounds__(256) k_leaf_gemm_f64(GemmArgs g) {
+  __shared__ int32_t s_slots[kWaves][128];
+  const int64_t node = uniform(xcd_contiguous_block() * kWaves + (threadIdx.x >> 6));
+  if (node >= g.n_nodes) return;
+  f64_block(g, node, threadIdx.x & 63, s_slots[threadIdx.x >> 6]);
+}
+
+__global__ void __launch_bounds__(256) k_leaf_gemm_f64_batch(GemmBatch b) {
+  __shared__ int32_t s_slots[kWaves][128];
+  int64_t node = uniform(xcd_contiguous_block() * kWaves + (threadIdx.x >> 6));
+  const GemmArgs* g = batch_locate(b, node);
+  if (!g) return;
+  f64_block(*g, node, threadIdx.x & 63, s_slots[threadIdx.x >> 6]);
 }
 
 // SP2 blocks of X_n with no executed product: C = 0 there, so
@@ -872,6 +914,40 @@ void launch_leaf_gemm(int prec, const GemmArgs& g, hipStream_t s) {
     k_leaf_gemm_f64<<<grid, 64 * kWaves, 0, s>>>(g);
   else
     k_leaf_gemm_f32<<<grid, 64 * kWaves, 0, s>>>(g);
+}
+
+void launch_leaf_gemm_batch(int prec, const GemmArgs* host, const GemmArgs* dev, int n,
+                            hipStream_t s) {
+  if (prec != SPAMM_FP64 && prec != SPAMM_FP32) {
+    launch_leaf_gemm_half_batch(prec, host, dev, n, s);
+    return;
+  }
+  const int choice = leaf_kernel_choice();
+  const bool grouped = prec == SPAMM_FP32 && (choice == kLeafW2x2 || choice == kLeafW2x2s);
+  if (prec == SPAMM_FP32 && !grouped && choice != kLeafBlock) {
+    for (int r = 0; r < n; ++r) launch_leaf_gemm(prec, host[r], s);
+    return;
+  }
+  auto grid = [](const GemmBatch& b) { return unsigned((b.first[b.n] + kWaves - 1) / kWaves); };
+  // 2 x 2 groups (FP32 with a tier d-1 frontier).
+  if (grouped) {
+    for_each_batch(dev, n, [&](int r) { return host[r].n_nodes > 0 ? host[r].n_super : 0; },
+                   [&](const GemmBatch& b) {
+                     if (choice == kLeafW2x2)
+                       k_leaf_gemm_f32_w2x2_batch<2><<<grid(b), 256, 0, s>>>(b);
+                     else
+                       k_leaf_gemm_f32_w2x2_batch<1><<<grid(b), 256, 0, s>>>(b);
+                   });
+  }
+  // One wave per C block: FP64, FP32 trees of one tier, FP32 "block".
+  for_each_batch(dev, n,
+                 [&](int r) { return grouped && host[r].n_super > 0 ? 0 : host[r].n_nodes; },
+                 [&](const GemmBatch& b) {
+                   if (prec == SPAMM_FP64)
+                     k_leaf_gemm_f64_batch<<<grid(b), 256, 0, s>>>(b);
+                   else
+                     k_leaf_gemm_f32_batch<<<grid(b), 256, 0, s>>>(b);
+                 });
 }
 
 void launch_sp2_rest(int prec, const RestArgs& r, hipStream_t s) {

@@ -145,13 +145,9 @@ __device__ inline void epilogue(const GemmArgs& g, int64_t node, int i, int j, c
 // One wave per 2 x 2 group of C blocks (tier d-1 node), operands in
 // registers, the next step's tiles in flight during the current products.
 template <int P>
-__global__ void __launch_bounds__(256) k_leaf_gemm_half_w2x2(GemmArgs g) {
+__device__ __forceinline__ void half_w2x2(const GemmArgs& g, int64_t p, int lane,
+                                          int32_t (*tab)[2 * kWBatch]) {
   typedef typename Half<P>::T T;
-  __shared__ int32_t s_tab[kWaves][5][2 * kWBatch];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t p = uniform(xcd_contiguous_block() * kWaves + wave);
-  if (p >= g.n_super) return;
-  int32_t(*tab)[2 * kWBatch] = s_tab[wave];
   const int32_t IJ = uniform(g.sup_nodes[p]);
   const int I = unpack_i(IJ), J = unpack_j(IJ);
   const int stride = (is_split(P) ? 4 : 2) * kLeaf2;
@@ -231,13 +227,29 @@ __global__ void __launch_bounds__(256) k_leaf_gemm_half_w2x2(GemmArgs g) {
   }
 }
 
+template <int P>
+__global__ void __launch_bounds__(256) k_leaf_gemm_half_w2x2(GemmArgs g) {
+  __shared__ int32_t s_tab[kWaves][5][2 * kWBatch];
+  const int wave = threadIdx.x >> 6;
+  const int64_t p = uniform(xcd_contiguous_block() * kWaves + wave);
+  if (p >= g.n_super) return;
+  half_w2x2<P>(g, p, threadIdx.x & 63, s_tab[wave]);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_leaf_gemm_half_w2x2_batch(GemmBatch b) {
+  __shared__ int32_t s_tab[kWaves][5][2 * kWBatch];
+  const int wave = threadIdx.x >> 6;
+  int64_t p = uniform(xcd_contiguous_block() * kWaves + wave);
+  const GemmArgs* g = batch_locate(b, p);
+  if (!g) return;
+  half_w2x2<P>(*g, p, threadIdx.x & 63, s_tab[wave]);
+}
+
 // One wave per C block over the leaf task list (trees of one tier).
 template <int P>
-__global__ void __launch_bounds__(256) k_leaf_gemm_half_block(GemmArgs g) {
+__device__ __forceinline__ void half_block(const GemmArgs& g, int64_t node, int lane) {
   typedef typename Half<P>::T T;
-  const int lane = threadIdx.x & 63;
-  const int64_t node = uniform(int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6));
-  if (node >= g.n_nodes) return;
   const int32_t ij = uniform(g.nodes[node]);
   const int i = unpack_i(ij), j = unpack_j(ij);
   const int stride = (is_split(P) ? 4 : 2) * kLeaf2;
@@ -255,6 +267,21 @@ __global__ void __launch_bounds__(256) k_leaf_gemm_half_block(GemmArgs g) {
     acc.add(fa, fb);
   }
   epilogue<P>(g, node, i, j, acc, lane);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_leaf_gemm_half_block(GemmArgs g) {
+  const int64_t node = uniform(int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6));
+  if (node >= g.n_nodes) return;
+  half_block<P>(g, node, threadIdx.x & 63);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_leaf_gemm_half_block_batch(GemmBatch b) {
+  int64_t node = uniform(int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6));
+  const GemmArgs* g = batch_locate(b, node);
+  if (!g) return;
+  half_block<P>(*g, node, threadIdx.x & 63);
 }
 
 // SP2 blocks of X_n with no executed product (see k_sp2_rest).
@@ -318,6 +345,15 @@ void launch_p(const GemmArgs& g, hipStream_t s) {
 }
 
 template <int P>
+void launch_batch_p(const GemmArgs* host, const GemmArgs* dev, int n, hipStream_t s) {
+  auto grid = [](const GemmBatch& b) { return unsigned((b.first[b.n] + kWaves - 1) / kWaves); };
+  for_each_batch(dev, n, [&](int r) { return host[r].n_nodes > 0 ? host[r].n_super : 0; },
+                 [&](const GemmBatch& b) { k_leaf_gemm_half_w2x2_batch<P><<<grid(b), 256, 0, s>>>(b); });
+  for_each_batch(dev, n, [&](int r) { return host[r].n_super > 0 ? 0 : host[r].n_nodes; },
+                 [&](const GemmBatch& b) { k_leaf_gemm_half_block_batch<P><<<grid(b), 256, 0, s>>>(b); });
+}
+
+template <int P>
 void launch_rest_p(const RestArgs& r, hipStream_t s) {
   k_sp2_rest_half<P><<<unsigned((r.n_x + kWaves - 1) / kWaves), 256, 0, s>>>(r);
 }
@@ -331,6 +367,17 @@ void launch_leaf_gemm_half(int prec, const GemmArgs& g, hipStream_t s) {
     case SPAMM_FP16: launch_p<SPAMM_FP16>(g, s); break;
     case SPAMM_BF16X3: launch_p<SPAMM_BF16X3>(g, s); break;
     case SPAMM_FP16X3: launch_p<SPAMM_FP16X3>(g, s); break;
+    default: break;
+  }
+}
+
+void launch_leaf_gemm_half_batch(int prec, const GemmArgs* host, const GemmArgs* dev, int n,
+                                 hipStream_t s) {
+  switch (prec) {
+    case SPAMM_BF16: launch_batch_p<SPAMM_BF16>(host, dev, n, s); break;
+    case SPAMM_FP16: launch_batch_p<SPAMM_FP16>(host, dev, n, s); break;
+    case SPAMM_BF16X3: launch_batch_p<SPAMM_BF16X3>(host, dev, n, s); break;
+    case SPAMM_FP16X3: launch_batch_p<SPAMM_FP16X3>(host, dev, n, s); break;
     default: break;
   }
 }

@@ -49,6 +49,44 @@ def test_struct_sizes_match_the_header():
     assert ctypes.sizeof(_lib.Sp2Options) == 32
     assert ctypes.sizeof(_lib.Sp2Stats) == 8 + 24 + 8 + 256 + 4 * 8 * 256
     assert ctypes.sizeof(_lib.Profile) == 6 * 8 * 2 + 8
+    assert ctypes.sizeof(_lib.ServerOptions) == 16
+    assert ctypes.sizeof(_lib.ServerInfo) == 11 * 8
+
+
+def test_server_options_defaults_and_host_side_argument_checks():
+    from paper_1403_7458_amd import _lib
+    lib = _lib.load()
+    o = _lib.ServerOptions()
+    lib.spamm_server_options_default(ctypes.byref(o))
+    assert (o.max_active, o.batch_gemm, o.device) == (64, 1, -1)
+    # Rejected before any device call: a zero budget, max_active out of range.
+    h = ctypes.c_void_p(1)
+    assert lib.spamm_server_create(0, ctypes.byref(o), ctypes.byref(h)) == -1
+    assert h.value is None
+    assert b"budget" in lib.spamm_last_error()
+    o.max_active = 0
+    assert lib.spamm_server_create(1 << 30, ctypes.byref(o), ctypes.byref(h)) == -1
+    lib.spamm_server_destroy(None)
+
+
+def test_sp2_footprint_bound():
+    """Host-only arithmetic: covers the tiles of X_n and X_{n+1} (up to
+    3 (ceil(n/32))^2 of them) plus dense copies of F and P, grows with n and
+    with the tile size, and is 0 for invalid arguments."""
+    import paper_1403_7458_amd as sp
+    tile = {"fp64": 8192, "fp32": 4096, "bf16": 4096, "fp16": 4096, "bf16x3": 8192,
+            "fp16x3": 8192}
+    for prec, tb in tile.items():
+        last = 0
+        for n in (1, 31, 32, 33, 180, 750, 3750, 10000):
+            rb = -(-n // 32)
+            b = sp.sp2_footprint_bytes(n, prec)
+            assert b >= 3 * rb * rb * tb + 2 * n * n * 8
+            assert b >= last
+            last = b
+    assert sp.sp2_footprint_bytes(3750, "fp64") > sp.sp2_footprint_bytes(3750, "fp32")
+    assert sp.sp2_footprint_bytes(0, "fp32") == 0
+    assert sp.sp2_footprint_bytes(100, 9) == 0
 
 
 def test_sp2_options_defaults_come_from_the_library():
