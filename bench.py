@@ -81,6 +81,118 @@ def cpu_baseline(x0: np.ndarray, tau: float, budget_s: float = 12.0):
                       f"FP64, recursive task form), median {t:.3f} s each"}
 
 
+def serving(args, sp, torch, dev, stream):
+    """Serving stream: requests of mixed size, decay and tau arriving as a
+    Poisson process, solved (a) one at a time with FP32 leaves in arrival
+    order, (b) by the lockstep server with FP32 leaves and (c) by the server
+    in the serving precision.  Latency = completion (P in device memory) -
+    scheduled arrival; solves/s = requests / (last completion - first
+    arrival).  Accuracy: ||P - P_64|| / ||P_64|| on a sample of requests,
+    P_64 from FP64 leaves at the same tau."""
+    from watergen import request_stream, water_cluster_torch
+    reqs = request_stream(count=args.serve_requests, rate_per_s=args.serve_rate,
+                          seed=args.serve_seed)
+    fs = [water_cluster_torch(r.molecules, r.decay, r.seed, device=dev) for r in reqs]
+    torch.cuda.synchronize()
+    sizes = [f.shape[0] for f, _ in fs]
+    order = np.argsort(sizes, kind="stable")
+    sample = sorted({int(order[0]), int(order[len(order) // 2]), int(order[-1])})
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(0.6 * free, 128 << 30))
+
+    def wait_until(t):
+        while True:
+            d = t - time.perf_counter()
+            if d <= 0:
+                return
+            time.sleep(min(d, 1e-3))
+
+    def leg(mode, prec):
+        k = len(reqs)
+        lat = [0.0] * k
+        keep = {}
+        iters = 0
+        srv = sp.Sp2Server(budget, max_active=64) if mode == "server" else None
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if srv is None:
+            for i, r in enumerate(reqs):
+                wait_until(t0 + r.arrival_s)
+                out = torch.empty_like(fs[i][0])
+                _, st = sp.sp2_solve(fs[i][0], fs[i][1], r.tau, out=out, precision=prec,
+                                     stream=stream)
+                lat[i] = time.perf_counter() - (t0 + r.arrival_s)
+                iters += st["iterations"]
+                if i in sample:
+                    keep[i] = out
+            end = time.perf_counter()
+            info = None
+        else:
+            pend, i, done = {}, 0, 0
+            while done < k:
+                now = time.perf_counter()
+                while i < k and t0 + reqs[i].arrival_s <= now:
+                    rid = srv.submit(fs[i][0], fs[i][1], reqs[i].tau, precision=prec)
+                    pend[rid] = (i, torch.empty_like(fs[i][0]))
+                    i += 1
+                moved = False
+                for rid in list(pend):
+                    j, out = pend[rid]
+                    res = srv.poll(rid, out=out)
+                    if res is not None:
+                        lat[j] = time.perf_counter() - (t0 + reqs[j].arrival_s)
+                        iters += res[1]["iterations"]
+                        if j in sample:
+                            keep[j] = out
+                        del pend[rid]
+                        done += 1
+                        moved = True
+                if not moved:
+                    time.sleep(2e-4)
+            end = time.perf_counter()
+            info = srv.stats()
+            srv.close()
+        res = {"precision": prec, "solves_per_s": round(k / (end - t0), 3),
+               "p50_ms": round(percentile(lat, 50) * 1e3, 2),
+               "p99_ms": round(percentile(lat, 99) * 1e3, 2),
+               "makespan_s": round(end - t0, 3), "sp2_iterations": iters}
+        if info is not None:
+            res["steps"] = info["steps"]
+            res["gemm_launches"] = info["gemm_launches"]
+            res["peak_used_gib"] = round(info["peak_used_bytes"] / 2 ** 30, 2)
+        return res, keep
+
+    # Warm-up of both paths (library set-up, pools) on the smallest request.
+    j0 = int(order[0])
+    sp.sp2_solve(fs[j0][0], fs[j0][1], reqs[j0].tau, out=torch.empty_like(fs[j0][0]),
+                 stream=stream)
+    with sp.Sp2Server(budget) as srv:
+        srv.wait(srv.submit(fs[j0][0], fs[j0][1], reqs[j0].tau, precision=args.serve_precision),
+                 out=torch.empty_like(fs[j0][0]))
+    legs = {}
+    outs = {}
+    for name, mode, prec in (("serial_fp32", "serial", "fp32"), ("server_fp32", "server", "fp32"),
+                             ("server_" + args.serve_precision, "server", args.serve_precision)):
+        legs[name], outs[name] = leg(mode, prec)
+        torch.cuda.synchronize()
+    for j in sample:
+        ref = torch.empty_like(fs[j][0])
+        sp.sp2_solve(fs[j][0], fs[j][1], reqs[j].tau, out=ref, precision="fp64", stream=stream)
+        torch.cuda.synchronize()
+        nr = float(torch.linalg.norm(ref))
+        for name in legs:
+            e = float(torch.linalg.norm(outs[name][j] - ref)) / nr
+            legs[name]["rel_err_vs_fp64_max"] = max(legs[name].get("rel_err_vs_fp64_max", 0.0), e)
+    return {
+        "workload": f"{len(reqs)} SP2 requests, Poisson arrivals at {args.serve_rate:g}/s "
+                    f"(stream seed {args.serve_seed}), molecules U{{30..400}} (N 750..10000), "
+                    "decay U[1.2, 2.5] A, tau in {1e-6, 1e-5}",
+        "n_range": [min(sizes), max(sizes)],
+        "accuracy_sample_n": [sizes[j] for j in sample],
+        "legs": legs,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -90,6 +202,11 @@ def main():
     ap.add_argument("--molecules", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-multiply", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests in the serving stream (0: skip the serving legs)")
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-seed", type=int, default=0)
+    ap.add_argument("--serve-precision", default="fp16x3")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -179,6 +296,10 @@ def main():
                 "err_bound": st["err_bound"]}
         mx.close()
 
+    serve = None
+    if args.serve_requests > 0:
+        serve = serving(args, sp, torch, dev, stream)
+
     cpu = None
     if not args.no_cpu_baseline:
         from oracle import sp2_oracle as sp2o
@@ -220,6 +341,7 @@ def main():
                 "leaf_products": execs, "trace_error": tr_err, "idempotency": idem},
         "phase_ms_per_step": phase_ms,
         "multiply": multiply,
+        "serving": serve,
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

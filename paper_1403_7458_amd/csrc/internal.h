@@ -300,29 +300,41 @@ void launch_leaf_gemm(int prec, const GemmArgs& g, hipStream_t s);
 void launch_leaf_gemm_half(int prec, const GemmArgs& g, hipStream_t s);
 
 // Batched launch: the leaf products of several independent products of one
-// precision in one grid.  Waves are numbered across the products in the
-// order of job[]; product job[r] owns waves [first[r], first[r + 1]) and
-// each wave runs exactly the work its index selects in a launch of that
-// product alone, so the results are bitwise those of separate launches.
+// precision in one grid.  Product job[r] owns workgroups [first[r],
+// first[r + 1]), a multiple of the XCD count, and its first items[r] waves
+// do exactly the work a launch of that product alone gives them, so the
+// results are bitwise those of separate launches.  Within its range each
+// product's workgroups map to its items XCD by XCD in contiguous runs, as in
+// a solo launch: workgroups are dispatched to the XCDs round-robin, so every
+// XCD gets an equal share of every product, whatever their sizes.
 constexpr int kMaxBatch = 64;
+constexpr int kBatchXcds = 8;
 struct GemmBatch {
   const GemmArgs* args;            // device array
   int32_t n;
+  int32_t waves_per_group;
   int32_t job[kMaxBatch];
+  int64_t items[kMaxBatch];
   int64_t first[kMaxBatch + 1];
 };
-// The product of wave `item` (rebased to that product), or NULL past the end.
-__device__ inline const GemmArgs* batch_locate(const GemmBatch& b, int64_t& item) {
-  if (item >= b.first[b.n]) return nullptr;
-  int lo = 0, hi = b.n - 1;  // largest r with first[r] <= item
+// The product of this wave (its item index in `item`), or NULL if the wave
+// has no work.
+__device__ inline const GemmArgs* batch_locate(const GemmBatch& b, int wave, int64_t& item) {
+  const int64_t wg = blockIdx.x;
+  if (wg >= b.first[b.n]) return nullptr;
+  int lo = 0, hi = b.n - 1;  // largest r with first[r] <= wg
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (b.first[mid] <= item)
+    if (b.first[mid] <= wg)
       lo = mid;
     else
       hi = mid - 1;
   }
-  item -= b.first[lo];
+  const int64_t local = wg - b.first[lo];
+  const int64_t per_xcd = (b.first[lo + 1] - b.first[lo]) / kBatchXcds;
+  const int64_t c = (local % kBatchXcds) * per_xcd + local / kBatchXcds;
+  item = c * b.waves_per_group + wave;
+  if (item >= b.items[lo]) return nullptr;
   return b.args + b.job[lo];
 }
 // host[r] and dev[r] hold the same arguments, on the host and the device;
@@ -332,19 +344,23 @@ void launch_leaf_gemm_batch(int prec, const GemmArgs* host, const GemmArgs* dev,
                             hipStream_t s);
 void launch_leaf_gemm_half_batch(int prec, const GemmArgs* host, const GemmArgs* dev, int n,
                                  hipStream_t s);
-// Fills groups of at most kMaxBatch products of one kind: items(r) is the
-// number of waves product r needs (0: skipped); emit(batch) launches.
+// Fills batches of at most kMaxBatch products of one kind: items(r) is the
+// number of waves product r needs (0: skipped), waves_per_group the waves
+// of a workgroup; emit(batch) launches first[n] workgroups.
 template <class Items, class Emit>
-void for_each_batch(const GemmArgs* dev, int n, Items items, Emit emit) {
+void for_each_batch(const GemmArgs* dev, int n, int waves_per_group, Items items, Emit emit) {
   GemmBatch b{};
   b.args = dev;
   b.n = 0;
+  b.waves_per_group = waves_per_group;
   b.first[0] = 0;
   for (int r = 0; r < n; ++r) {
     const int64_t w = items(r);
     if (w <= 0) continue;
+    const int64_t groups = (w + waves_per_group - 1) / waves_per_group;
     b.job[b.n] = r;
-    b.first[b.n + 1] = b.first[b.n] + w;
+    b.items[b.n] = w;
+    b.first[b.n + 1] = b.first[b.n] + (groups + kBatchXcds - 1) / kBatchXcds * kBatchXcds;
     if (++b.n == kMaxBatch) {
       emit(b);
       b.n = 0;

@@ -198,8 +198,8 @@ __global__ void __launch_bounds__(256) k_leaf_gemm_f32(GemmArgs g) {
 
 __global__ void __launch_bounds__(256) k_leaf_gemm_f32_batch(GemmBatch b) {
   __shared__ int32_t s_slots[kWaves][128];
-  int64_t node = uniform(xcd_contiguous_block() * kWaves + (threadIdx.x >> 6));
-  const GemmArgs* g = batch_locate(b, node);
+  int64_t node = 0;
+  const GemmArgs* g = batch_locate(b, threadIdx.x >> 6, node);
   if (!g) return;
   f32_block(*g, node, threadIdx.x & 63, s_slots[threadIdx.x >> 6]);
 }
@@ -514,8 +514,8 @@ template <int kAhead>
 __global__ void __launch_bounds__(256) k_leaf_gemm_f32_w2x2_batch(GemmBatch b) {
   __shared__ int32_t s_tab[kWaves][5][2 * kWBatch];
   const int wave = threadIdx.x >> 6;
-  int64_t p = uniform(xcd_contiguous_block() * kWaves + wave);
-  const GemmArgs* g = batch_locate(b, p);
+  int64_t p = 0;
+  const GemmArgs* g = batch_locate(b, wave, p);
   if (!g) return;
   f32_w2x2<kAhead>(*g, p, threadIdx.x & 63, s_tab[wave]);
 }
@@ -770,8 +770,8 @@ __global__ void __launch_bounds__(256) k_leaf_gemm_f64(GemmArgs g) {
 
 __global__ void __launch_bounds__(256) k_leaf_gemm_f64_batch(GemmBatch b) {
   __shared__ int32_t s_slots[kWaves][128];
-  int64_t node = uniform(xcd_contiguous_block() * kWaves + (threadIdx.x >> 6));
-  const GemmArgs* g = batch_locate(b, node);
+  int64_t node = 0;
+  const GemmArgs* g = batch_locate(b, threadIdx.x >> 6, node);
   if (!g) return;
   f64_block(*g, node, threadIdx.x & 63, s_slots[threadIdx.x >> 6]);
 }
@@ -928,10 +928,10 @@ void launch_leaf_gemm_batch(int prec, const GemmArgs* host, const GemmArgs* dev,
     for (int r = 0; r < n; ++r) launch_leaf_gemm(prec, host[r], s);
     return;
   }
-  auto grid = [](const GemmBatch& b) { return unsigned((b.first[b.n] + kWaves - 1) / kWaves); };
+  auto grid = [](const GemmBatch& b) { return unsigned(b.first[b.n]); };
   // 2 x 2 groups (FP32 with a tier d-1 frontier).
   if (grouped) {
-    for_each_batch(dev, n, [&](int r) { return host[r].n_nodes > 0 ? host[r].n_super : 0; },
+    for_each_batch(dev, n, kWaves, [&](int r) { return host[r].n_nodes > 0 ? host[r].n_super : 0; },
                    [&](const GemmBatch& b) {
                      if (choice == kLeafW2x2)
                        k_leaf_gemm_f32_w2x2_batch<2><<<grid(b), 256, 0, s>>>(b);
@@ -940,7 +940,7 @@ void launch_leaf_gemm_batch(int prec, const GemmArgs* host, const GemmArgs* dev,
                    });
   }
   // One wave per C block: FP64, FP32 trees of one tier, FP32 "block".
-  for_each_batch(dev, n,
+  for_each_batch(dev, n, kWaves,
                  [&](int r) { return grouped && host[r].n_super > 0 ? 0 : host[r].n_nodes; },
                  [&](const GemmBatch& b) {
                    if (prec == SPAMM_FP64)

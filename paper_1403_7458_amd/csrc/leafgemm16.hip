@@ -240,8 +240,8 @@ template <int P>
 __global__ void __launch_bounds__(256) k_leaf_gemm_half_w2x2_batch(GemmBatch b) {
   __shared__ int32_t s_tab[kWaves][5][2 * kWBatch];
   const int wave = threadIdx.x >> 6;
-  int64_t p = uniform(xcd_contiguous_block() * kWaves + wave);
-  const GemmArgs* g = batch_locate(b, p);
+  int64_t p = 0;
+  const GemmArgs* g = batch_locate(b, wave, p);
   if (!g) return;
   half_w2x2<P>(*g, p, threadIdx.x & 63, s_tab[wave]);
 }
@@ -278,8 +278,8 @@ __global__ void __launch_bounds__(256) k_leaf_gemm_half_block(GemmArgs g) {
 
 template <int P>
 __global__ void __launch_bounds__(256) k_leaf_gemm_half_block_batch(GemmBatch b) {
-  int64_t node = uniform(int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6));
-  const GemmArgs* g = batch_locate(b, node);
+  int64_t node = 0;
+  const GemmArgs* g = batch_locate(b, threadIdx.x >> 6, node);
   if (!g) return;
   half_block<P>(*g, node, threadIdx.x & 63);
 }
@@ -346,10 +346,10 @@ void launch_p(const GemmArgs& g, hipStream_t s) {
 
 template <int P>
 void launch_batch_p(const GemmArgs* host, const GemmArgs* dev, int n, hipStream_t s) {
-  auto grid = [](const GemmBatch& b) { return unsigned((b.first[b.n] + kWaves - 1) / kWaves); };
-  for_each_batch(dev, n, [&](int r) { return host[r].n_nodes > 0 ? host[r].n_super : 0; },
+  auto grid = [](const GemmBatch& b) { return unsigned(b.first[b.n]); };
+  for_each_batch(dev, n, kWaves, [&](int r) { return host[r].n_nodes > 0 ? host[r].n_super : 0; },
                  [&](const GemmBatch& b) { k_leaf_gemm_half_w2x2_batch<P><<<grid(b), 256, 0, s>>>(b); });
-  for_each_batch(dev, n, [&](int r) { return host[r].n_super > 0 ? 0 : host[r].n_nodes; },
+  for_each_batch(dev, n, kWaves, [&](int r) { return host[r].n_super > 0 ? 0 : host[r].n_nodes; },
                  [&](const GemmBatch& b) { k_leaf_gemm_half_block_batch<P><<<grid(b), 256, 0, s>>>(b); });
 }
 

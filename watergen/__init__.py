@@ -6,8 +6,9 @@ SpAMM or SP2 arithmetic.
 from .cluster import (BASIS_PER_MOLECULE, OCC_PER_MOLECULE, Request, WaterCluster,
                       lattice_sites, molecule_centres, request_seed, request_stream,
                       water_cluster)
+from .cluster_torch import water_cluster_torch
 from .hilbert import hilbert_index, transpose_index
 
 __all__ = ["BASIS_PER_MOLECULE", "OCC_PER_MOLECULE", "Request", "WaterCluster",
            "lattice_sites", "molecule_centres", "request_seed", "request_stream",
-           "water_cluster", "hilbert_index", "transpose_index"]
+           "water_cluster", "water_cluster_torch", "hilbert_index", "transpose_index"]
