@@ -202,7 +202,7 @@ def main():
     ap.add_argument("--molecules", type=int, default=150)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-multiply", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=48,
+    ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests in the serving stream (0: skip the serving legs)")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-seed", type=int, default=0)

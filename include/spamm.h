@@ -241,7 +241,8 @@ size_t sp2_footprint_bytes(int64_t n, int32_t prec);
  * A server owns a worker thread and a stream (default priority) on one
  * device.  Requests are admitted first come, first served, while the sum of
  * sp2_footprint_bytes over the running requests and the results not yet
- * collected fits in the budget.  Each step runs one SP2 iteration of every
+ * collected fits in the budget, a slot is free, and the running requests
+ * leave the device room (fill_products).  Each step runs one SP2 iteration of every
  * running request: the leaf products of all requests of one precision go to
  * one batched launch, the occlusion passes and epilogues of the requests are
  * queued behind it, and the step ends with one synchronisation.  Every
@@ -255,7 +256,9 @@ typedef struct spamm_server_options {
     int32_t batch_gemm;  /* 1 (default): one leaf-product launch per precision
                             and step; 0: one launch per request */
     int32_t device;      /* HIP device; -1 (default): the current device */
-    int32_t reserved;
+    int32_t fill_products; /* admit more requests only while the running ones
+                              execute fewer leaf products per step than this
+                              (default 2^18; 0: no limit) */
 } spamm_server_options;
 
 typedef struct spamm_server_info {

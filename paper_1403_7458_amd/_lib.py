@@ -73,7 +73,7 @@ class Profile(ctypes.Structure):
 
 class ServerOptions(ctypes.Structure):
     _fields_ = [("max_active", ctypes.c_int32), ("batch_gemm", ctypes.c_int32),
-                ("device", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("device", ctypes.c_int32), ("fill_products", ctypes.c_int32)]
 
 
 class ServerInfo(ctypes.Structure):
@@ -334,11 +334,13 @@ class Sp2Server:
     device, one iteration of every running request per step."""
 
     def __init__(self, budget_bytes: int, max_active: int = 64, batch_gemm: bool = True,
-                 device: int = -1):
+                 device: int = -1, fill_products=None):
         lib = load()
         o = ServerOptions()
         lib.spamm_server_options_default(ctypes.byref(o))
         o.max_active, o.batch_gemm, o.device = int(max_active), int(bool(batch_gemm)), int(device)
+        if fill_products is not None:
+            o.fill_products = int(fill_products)
         self._h = ctypes.c_void_p()
         _check(lib.spamm_server_create(int(budget_bytes), ctypes.byref(o), ctypes.byref(self._h)))
         self._inputs = {}   # device inputs, kept alive until their request finishes

@@ -347,6 +347,10 @@ Error alloc_pool(spamm_matrix* m, int64_t cap_blocks, hipStream_t s) {
 
 void free_matrix(spamm_matrix* m) {
   if (!m) return;
+  if (!m->owns) {
+    delete m;
+    return;
+  }
   dev_free(m->pool, m->stream);
   dev_free(m->coords, m->stream);
   dev_free(m->map, m->stream);

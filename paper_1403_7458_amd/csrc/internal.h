@@ -74,6 +74,11 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   Error reserve(size_t want, hipStream_t s);
+  // As reserve, but a regrowth takes 25% headroom (buffers that creep up).
+  Error grow(size_t want, hipStream_t s) {
+    if (want <= bytes && p) return Error{};
+    return reserve(want + want / 4, s);
+  }
   void release(hipStream_t s);
 };
 
@@ -103,6 +108,7 @@ struct spamm_matrix {
   int32_t* coords = nullptr;
   double* norms = nullptr;
   double frob = 0.0;
+  bool owns = true;  // false: the buffers belong to a workspace (SP2 iterates)
 };
 
 namespace spamm {
@@ -437,15 +443,39 @@ struct DenseIn {
 
 // Per-thread reusable workspace of the culling pass, kept for the life of
 // the thread (never destroyed, so no HIP call runs from a static destructor).
-struct Workspace {
+// Grow-only buffers of one SP2 iterate (block map, norm pyramid, tile pool,
+// slot coordinates), reused from iteration to iteration: X_{n+1} takes the
+// buffers X_{n-1} held.
+struct IterBuf {
+  DevBuf map, norms, pool, coords;
+  void release(hipStream_t s) {
+    map.release(s);
+    norms.release(s);
+    pool.release(s);
+    coords.release(s);
+  }
+};
+// What one SP2 solve reuses: the culling workspace and two iterate buffers.
+struct Sp2Work {
   CullWork cull;
+  IterBuf iter[2];
+  void release(hipStream_t s) {
+    cull.release(s);
+    iter[0].release(s);
+    iter[1].release(s);
+  }
+};
+
+struct Workspace {
+  Sp2Work sp2;
+  CullWork& cull = sp2.cull;
   hipStream_t last = nullptr;
   bool used = false;
   int device = -1;
   void bind(hipStream_t s) {
     const int d = current_device();
     if (device != d) {
-      if (used) cull.release(last);
+      if (used) sp2.release(last);
       device = d;
     }
     if (used && last != s) (void)hipStreamSynchronize(last);

@@ -96,8 +96,8 @@ Error sp2_ingest(const double* f, int64_t ldf, int64_t n, int prec, Sp2Buffers& 
 class Sp2Job {
  public:
   Sp2Job(int64_t n, int64_t n_occ, double tau, const sp2_options& opt, hipStream_t s,
-         CullWork* w)
-      : n_(n), n_occ_(n_occ), tau_(tau), opt_(opt), s_(s), w_(w) {
+         Sp2Work* work)
+      : n_(n), n_occ_(n_occ), tau_(tau), opt_(opt), s_(s), w_(&work->cull), iter_(work->iter) {
     buf_.s = s;
     std::memset(&st_, 0, sizeof(st_));
     double floor_rel = opt.stall_floor;
@@ -135,8 +135,8 @@ class Sp2Job {
   Error front(GemmArgs* g, int64_t* products) {
     square_ = t_n_ > double(n_occ_);
     const int nb = x_->nb;
-    SPAMM_TRY(new_matrix(n_, opt_.precision, s_, &y_));
-    SPAMM_TRY(alloc_pool(y_, std::max<int64_t>(cr_.n_cblocks + (square_ ? 0 : x_->n_blocks), 1), s_));
+    SPAMM_TRY(iterate(iter_[it_ & 1],
+                      std::max<int64_t>(cr_.n_cblocks + (square_ ? 0 : x_->n_blocks), 1), &y_));
     Control* ctl = w_->ctl_dev;
     launch_sp2_prepare(y_->map, y_->norms + tier_offset(y_->depth), buf_.err_part, nb,
                        buf_.trace_part, &ctl->scratch[1], s_);
@@ -256,6 +256,7 @@ class Sp2Job {
   void output(double* p_dev, int64_t ldp) { launch_to_dense(x_, p_dev, ldp, s_); }
 
   bool done() const { return done_; }
+  int64_t next_products() const { return cr_.n_tasks; }
   int status() const { return stop_ == SP2_STOP_MAX_ITER ? SPAMM_NOT_CONVERGED : SPAMM_OK; }
   const sp2_stats& stats() const { return st_; }
   int prec() const { return opt_.precision; }
@@ -267,11 +268,38 @@ class Sp2Job {
   }
 
  private:
+  // X_{n+1} in the workspace buffers b (those of X_{n-1}, whose last reader
+  // ran earlier on the stream), grown to hold `cap` blocks.
+  Error iterate(IterBuf& b, int64_t cap, spamm_matrix** out) {
+    const int nb = x_->nb, depth = x_->depth;
+    SPAMM_TRY(b.map.grow(size_t(nb) * nb * sizeof(int32_t), s_));
+    SPAMM_TRY(b.norms.grow(size_t(norms_size(depth)) * sizeof(double), s_));
+    SPAMM_TRY(b.pool.grow(size_t(cap) * tile_bytes(opt_.precision), s_));
+    SPAMM_TRY(b.coords.grow(size_t(cap) * sizeof(int32_t), s_));
+    spamm_matrix* m = new spamm_matrix();
+    m->n = n_;
+    m->n_pad = x_->n_pad;
+    m->nb = nb;
+    m->depth = depth;
+    m->prec = opt_.precision;
+    m->device = x_->device;
+    m->stream = s_;
+    m->cap_blocks = cap;
+    m->pool = b.pool.p;
+    m->map = static_cast<int32_t*>(b.map.p);
+    m->coords = static_cast<int32_t*>(b.coords.p);
+    m->norms = static_cast<double*>(b.norms.p);
+    m->owns = false;
+    *out = m;
+    return Error{};
+  }
+
   int64_t n_, n_occ_;
   double tau_;
   sp2_options opt_;
   hipStream_t s_;
   CullWork* w_;
+  IterBuf* iter_;
   Sp2Buffers buf_;
   Scale sh_{};
   spamm_matrix* x_ = nullptr;  // X_n
@@ -303,7 +331,7 @@ Error sp2_impl(const double* f, int64_t n, int64_t ldf, int64_t n_occ, double ta
   ws().bind(s);
   DenseIn in;
   SPAMM_TRY(in.take(f, n, ldf, s));
-  Sp2Job job(n, n_occ, tau, opt, s, &ws().cull);
+  Sp2Job job(n, n_occ, tau, opt, s, &ws().sp2);
   SPAMM_TRY(job.begin(in.p, in.ld));
   SPAMM_TRY(sync(s));
   SPAMM_TRY(job.begun());
@@ -417,7 +445,7 @@ struct Request {
   std::vector<double> f_host;     // copy of a host input
   size_t reserve = 0;
   // Running.
-  std::unique_ptr<CullWork> work;
+  std::unique_ptr<Sp2Work> work;
   std::unique_ptr<Sp2Job> job;
   GemmArgs g{};
   int64_t products = 0;
@@ -445,7 +473,7 @@ struct spamm_server {
   std::condition_variable cv_work, cv_done;
   std::deque<Request*> queue;
   std::map<uint64_t, Request*> all;  // every request not yet polled
-  std::vector<std::unique_ptr<CullWork>> spare;
+  std::vector<std::unique_ptr<Sp2Work>> spare;
   uint64_t next_id = 1;
   bool stopping = false;
   spamm_server_info st{};
@@ -476,7 +504,7 @@ Error spamm_server::start(Request* r) {
       spare.pop_back();
     }
   }
-  if (!r->work) r->work.reset(new CullWork());
+  if (!r->work) r->work.reset(new Sp2Work());
   r->job.reset(new Sp2Job(r->n, r->n_occ, r->tau, r->opt, stream, r->work.get()));
   double* staged = nullptr;
   const double* f = r->f_dev;
@@ -501,7 +529,7 @@ void spamm_server::finish(Request* r, const Error& e) {
     if (e.ok()) r->stats = r->job->stats();
     r->job.reset();
   }
-  std::unique_ptr<CullWork> w = std::move(r->work);
+  std::unique_ptr<Sp2Work> w = std::move(r->work);
   if (w) w->release(stream);
   std::lock_guard<std::mutex> lk(mu);
   if (w) spare.push_back(std::move(w));
@@ -526,40 +554,49 @@ void spamm_server::run() {
   (void)hipSetDevice(device);
   std::vector<Request*> running;
   for (;;) {
-    std::vector<Request*> admitted;
-    {
-      std::unique_lock<std::mutex> lk(mu);
-      for (;;) {
-        // FIFO admission: the head of the queue enters when its footprint
-        // fits in what the budget has left (and a slot is free).
-        while (!queue.empty() && int64_t(running.size() + admitted.size()) < opt.max_active &&
-               queue.front()->reserve <= budget - std::min(budget, size_t(st.used_bytes))) {
-          Request* r = queue.front();
-          queue.pop_front();
-          st.queued -= 1;
-          st.active += 1;
-          st.used_bytes += r->reserve;
-          st.peak_used_bytes = std::max(st.peak_used_bytes, st.used_bytes);
-          admitted.push_back(r);
+    // Admission, first come first served: the head of the queue starts when
+    // its footprint fits in what the budget has left, a slot is free and
+    // the running requests' leaf products per step are below fill_products
+    // (so a request that fills the device alone runs alone, and small ones
+    // share steps).
+    bool stop_now = false;
+    for (;;) {
+      Request* r = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+          if (stopping) {
+            stop_now = true;
+            break;
+          }
+          int64_t load = 0;
+          for (const Request* q : running) load += q->products;
+          if (!queue.empty() && int64_t(running.size()) < opt.max_active &&
+              queue.front()->reserve <= budget - std::min(budget, size_t(st.used_bytes)) &&
+              (opt.fill_products <= 0 || running.empty() || load < opt.fill_products)) {
+            r = queue.front();
+            queue.pop_front();
+            st.queued -= 1;
+            st.active += 1;
+            st.used_bytes += r->reserve;
+            st.peak_used_bytes = std::max(st.peak_used_bytes, st.used_bytes);
+            break;
+          }
+          if (!running.empty()) break;
+          cv_work.wait(lk);
         }
-        if (stopping || !running.empty() || !admitted.empty()) break;
-        cv_work.wait(lk);
       }
-      if (stopping) {
-        lk.unlock();
-        for (Request* r : admitted) running.push_back(r);
-        break;
-      }
-    }
-    for (Request* r : admitted) {
+      if (stop_now || !r) break;
       Error e = start(r);
       if (e.ok()) {
+        r->products = r->job->next_products();
         running.push_back(r);
       } else {
         (void)hipStreamSynchronize(stream);
         finish(r, e);
       }
     }
+    if (stop_now) break;
     if (running.empty()) continue;
     // One iteration of every running solve: the leaf products of each
     // precision in one launch.
@@ -678,6 +715,7 @@ void spamm_server_options_default(spamm_server_options* o) {
   o->max_active = 64;
   o->batch_gemm = 1;
   o->device = -1;
+  o->fill_products = 1 << 18;
 }
 
 int spamm_server_create(size_t hbm_budget_bytes, const spamm_server_options* o,
@@ -689,6 +727,7 @@ int spamm_server_create(size_t hbm_budget_bytes, const spamm_server_options* o,
   if (o) opt = *o;
   if (opt.max_active < 1 || opt.max_active > 1024)
     return fail(SPAMM_ERR_INVALID_ARG, "need 1 <= max_active <= 1024");
+  if (opt.fill_products < 0) return fail(SPAMM_ERR_INVALID_ARG, "need fill_products >= 0");
   if (hbm_budget_bytes == 0) return fail(SPAMM_ERR_INVALID_ARG, "budget must be > 0");
   int dev = opt.device;
   if (dev < 0) dev = current_device();

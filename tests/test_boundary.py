@@ -58,7 +58,7 @@ def test_server_options_defaults_and_host_side_argument_checks():
     lib = _lib.load()
     o = _lib.ServerOptions()
     lib.spamm_server_options_default(ctypes.byref(o))
-    assert (o.max_active, o.batch_gemm, o.device) == (64, 1, -1)
+    assert (o.max_active, o.batch_gemm, o.device, o.fill_products) == (64, 1, -1, 1 << 18)
     # Rejected before any device call: a zero budget, max_active out of range.
     h = ctypes.c_void_p(1)
     assert lib.spamm_server_create(0, ctypes.byref(o), ctypes.byref(h)) == -1

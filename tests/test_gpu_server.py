@@ -95,6 +95,18 @@ def test_device_inputs_unbatched_launches_and_device_outputs(sp, inputs, alone):
     assert info["gemm_launches"] == info["solve_iterations"]
 
 
+def test_fill_limit_runs_requests_one_at_a_time(sp, inputs, alone):
+    """fill_products = 1: any running request fills the device, so requests
+    run one after another (one launch per SP2 iteration), same results."""
+    with sp.Sp2Server(8 << 30, fill_products=1) as srv:
+        ids = [srv.submit(wc.f, wc.n_occ, tau, precision=prec)
+               for wc, (_, _, _, prec, tau) in zip(inputs, CASES)]
+        for rid, ref in zip(ids, alone):
+            same(srv.wait(rid), ref)
+        info = srv.stats()
+    assert info["gemm_launches"] == info["solve_iterations"] == info["steps"]
+
+
 def test_small_budget_queues_requests_and_stays_within_it(sp, inputs, alone):
     """A budget a little above the largest request admits one request at a
     time (plus nothing else while its result is held), in FIFO order."""
