@@ -240,9 +240,11 @@ size_t sp2_footprint_bytes(int64_t n, int32_t prec);
  *
  * A server owns a worker thread and a stream (default priority) on one
  * device.  Requests are admitted first come, first served, while the sum of
- * sp2_footprint_bytes over the running requests and the results not yet
- * collected fits in the budget, a slot is free, and the running requests
- * leave the device room (fill_products).  Each step runs one SP2 iteration of every
+ * sp2_footprint_bytes over the running requests, the results not yet
+ * collected and the buffers finished requests left for reuse fits in the
+ * budget (those buffers are dropped first when the next request would not
+ * fit), a slot is free, and the running requests leave the device room
+ * (fill_products).  Each step runs one SP2 iteration of every
  * running request: the leaf products of all requests of one precision go to
  * one batched launch, the occlusion passes and epilogues of the requests are
  * queued behind it, and the step ends with one synchronisation.  Every
@@ -267,7 +269,10 @@ typedef struct spamm_server_info {
     int64_t steps;                         /* lockstep iterations run */
     int64_t gemm_launches;                 /* leaf-product launches */
     int64_t solve_iterations;              /* SP2 iterations of completed requests */
-    uint64_t budget_bytes, used_bytes, peak_used_bytes;
+    uint64_t budget_bytes;
+    uint64_t used_bytes;      /* footprints of running requests + results held */
+    uint64_t cached_bytes;    /* buffers idle workspaces keep for reuse */
+    uint64_t peak_used_bytes; /* peak of used + cached (<= budget) */
 } spamm_server_info;
 
 void spamm_server_options_default(spamm_server_options* o);

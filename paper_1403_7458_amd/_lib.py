@@ -82,7 +82,7 @@ class ServerInfo(ctypes.Structure):
                 ("active", ctypes.c_int64), ("steps", ctypes.c_int64),
                 ("gemm_launches", ctypes.c_int64), ("solve_iterations", ctypes.c_int64),
                 ("budget_bytes", ctypes.c_uint64), ("used_bytes", ctypes.c_uint64),
-                ("peak_used_bytes", ctypes.c_uint64)]
+                ("cached_bytes", ctypes.c_uint64), ("peak_used_bytes", ctypes.c_uint64)]
 
 
 # Exported symbols and their signatures (kept in step with include/spamm.h).

@@ -10,6 +10,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -74,10 +75,11 @@ struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
   Error reserve(size_t want, hipStream_t s);
-  // As reserve, but a regrowth takes 25% headroom (buffers that creep up).
-  Error grow(size_t want, hipStream_t s) {
+  // As reserve, but a regrowth takes 25% headroom (buffers that creep up),
+  // never past `limit` bytes.
+  Error grow(size_t want, hipStream_t s, size_t limit = SIZE_MAX) {
     if (want <= bytes && p) return Error{};
-    return reserve(want + want / 4, s);
+    return reserve(std::max(want, std::min(want + want / 4, limit)), s);
   }
   void release(hipStream_t s);
 };
@@ -195,6 +197,11 @@ struct CullWork {
   Control* ctl_dev = nullptr;
   Control* ctl_host = nullptr;  // pinned
   void release(hipStream_t s);
+  size_t held_bytes() const {
+    size_t b = cnt4.bytes + toff.bytes + noff.bytes + part.bytes + bits.bytes + quad.bytes;
+    for (int t = 0; t < kMaxTiers; ++t) b += nodes[t].bytes + nptr[t].bytes + ks[t].bytes;
+    return b;
+  }
   ~CullWork();
 };
 
@@ -339,9 +346,15 @@ __device__ inline const GemmArgs* batch_locate(const GemmBatch& b, int wave, int
   const int64_t local = wg - b.first[lo];
   const int64_t per_xcd = (b.first[lo + 1] - b.first[lo]) / kBatchXcds;
   const int64_t c = (local % kBatchXcds) * per_xcd + local / kBatchXcds;
-  item = c * b.waves_per_group + wave;
+  // The wave index is uniform across the wave; saying so keeps the item,
+  // and every branch and address derived from it, in scalar registers.
+  item = c * b.waves_per_group + __builtin_amdgcn_readfirstlane(wave);
   if (item >= b.items[lo]) return nullptr;
-  return b.args + b.job[lo];
+  // The arguments are read through the constant address space, as kernel
+  // arguments are: no store of the kernel can change them, so the compiler
+  // reads them with scalar loads and branches on them uniformly.
+  typedef const __attribute__((address_space(4))) GemmArgs ConstArgs;
+  return (const GemmArgs*)((ConstArgs*)(b.args) + b.job[lo]);
 }
 // host[r] and dev[r] hold the same arguments, on the host and the device;
 // every product is of precision prec.  Products whose kernel has no batched
@@ -454,6 +467,7 @@ struct IterBuf {
     pool.release(s);
     coords.release(s);
   }
+  size_t held_bytes() const { return map.bytes + norms.bytes + pool.bytes + coords.bytes; }
 };
 // What one SP2 solve reuses: the culling workspace and two iterate buffers.
 struct Sp2Work {
@@ -463,6 +477,9 @@ struct Sp2Work {
     cull.release(s);
     iter[0].release(s);
     iter[1].release(s);
+  }
+  size_t held_bytes() const {
+    return cull.held_bytes() + iter[0].held_bytes() + iter[1].held_bytes();
   }
 };
 

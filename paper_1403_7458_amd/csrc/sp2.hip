@@ -272,10 +272,13 @@ class Sp2Job {
   // ran earlier on the stream), grown to hold `cap` blocks.
   Error iterate(IterBuf& b, int64_t cap, spamm_matrix** out) {
     const int nb = x_->nb, depth = x_->depth;
+    // At most twice the real blocks: C's blocks plus X_n's.
+    const int64_t rb = (n_ + kLeaf - 1) / kLeaf, most = 2 * rb * rb;
     SPAMM_TRY(b.map.grow(size_t(nb) * nb * sizeof(int32_t), s_));
     SPAMM_TRY(b.norms.grow(size_t(norms_size(depth)) * sizeof(double), s_));
-    SPAMM_TRY(b.pool.grow(size_t(cap) * tile_bytes(opt_.precision), s_));
-    SPAMM_TRY(b.coords.grow(size_t(cap) * sizeof(int32_t), s_));
+    SPAMM_TRY(b.pool.grow(size_t(cap) * tile_bytes(opt_.precision), s_,
+                          size_t(most) * tile_bytes(opt_.precision)));
+    SPAMM_TRY(b.coords.grow(size_t(cap) * sizeof(int32_t), s_, size_t(most) * sizeof(int32_t)));
     spamm_matrix* m = new spamm_matrix();
     m->n = n_;
     m->n_pad = x_->n_pad;
@@ -368,10 +371,11 @@ Error sp2_impl(const double* f, int64_t n, int64_t ldf, int64_t n_occ, double ta
 }  // namespace
 
 // Device memory an SP2 solve of order n holds at its peak (an upper bound
-// over the fill-in SpAMM allows): tiles of X_n and of X_{n+1} (up to twice
-// the real blocks in the 2X - X^2 branch), both trees' maps and pyramids,
-// a dense FP64 staging copy of F and the dense result, the SP2 partial
-// sums and a culling workspace sized for the dense task count.
+// over the fill-in SpAMM allows): the two iterate buffers (each up to twice
+// the real blocks: C's blocks plus X_n's in the 2X - X^2 branch), both
+// trees' maps and pyramids, a dense FP64 staging copy of F and the dense
+// result, the SP2 partial sums and a culling workspace sized for the dense
+// task count.
 size_t footprint_bytes(int64_t n, int prec) {
   int nb = 1, depth = 0;
   while (int64_t(kLeaf) * nb < n) {
@@ -380,7 +384,7 @@ size_t footprint_bytes(int64_t n, int prec) {
   }
   const double rb = double((n + kLeaf - 1) / kLeaf);
   const double cells = double(nb) * nb;
-  double b = 3.0 * rb * rb * double(tile_bytes(prec));
+  double b = 4.0 * rb * rb * (double(tile_bytes(prec)) + 4.0);
   b += 2.0 * (cells * 8.0 + double(norms_size(depth)) * 8.0);
   b += 2.0 * double(n) * double(n) * 8.0;
   b += cells * 8.0 + double(nb) * 8.0 + 3.0 * double(n) * 8.0;
@@ -444,6 +448,7 @@ struct Request {
   int64_t ldf = 0;
   std::vector<double> f_host;     // copy of a host input
   size_t reserve = 0;
+  size_t accounted = 0;           // bytes counted in used_bytes while running
   // Running.
   std::unique_ptr<Sp2Work> work;
   std::unique_ptr<Sp2Job> job;
@@ -473,6 +478,8 @@ struct spamm_server {
   std::condition_variable cv_work, cv_done;
   std::deque<Request*> queue;
   std::map<uint64_t, Request*> all;  // every request not yet polled
+  // Workspaces of finished requests, kept with their buffers (counted in
+  // cached_bytes) so that later requests reuse them instead of allocating.
   std::vector<std::unique_ptr<Sp2Work>> spare;
   uint64_t next_id = 1;
   bool stopping = false;
@@ -482,6 +489,29 @@ struct spamm_server {
   void run();
   void finish(Request* r, const Error& e);
   Error start(Request* r);
+  // Under mu: whether q fits with the newest spare workspace, then takes it.
+  bool fits(const Request* q) const {
+    const size_t h = spare.empty() ? 0 : spare.back()->held_bytes();
+    const size_t acc = std::max(q->reserve, h);
+    return st.used_bytes + acc + (st.cached_bytes - h) <= budget;
+  }
+  void admit(Request* r) {
+    const size_t h = spare.empty() ? 0 : spare.back()->held_bytes();
+    if (!spare.empty()) {
+      r->work = std::move(spare.back());
+      spare.pop_back();
+    }
+    st.cached_bytes -= h;
+    r->accounted = std::max(r->reserve, h);
+    st.used_bytes += r->accounted;
+    st.queued -= 1;
+    st.active += 1;
+    st.peak_used_bytes = std::max(st.peak_used_bytes, st.used_bytes + st.cached_bytes);
+  }
+  void trim_cache() {
+    for (auto& w : spare) w->release(stream);
+    st.cached_bytes = 0;
+  }
 };
 
 namespace {
@@ -497,13 +527,6 @@ Error stage_host_input(Request* r, hipStream_t s, double** f_dev) {
 }  // namespace
 
 Error spamm_server::start(Request* r) {
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    if (!spare.empty()) {
-      r->work = std::move(spare.back());
-      spare.pop_back();
-    }
-  }
   if (!r->work) r->work.reset(new Sp2Work());
   r->job.reset(new Sp2Job(r->n, r->n_occ, r->tau, r->opt, stream, r->work.get()));
   double* staged = nullptr;
@@ -530,18 +553,21 @@ void spamm_server::finish(Request* r, const Error& e) {
     r->job.reset();
   }
   std::unique_ptr<Sp2Work> w = std::move(r->work);
-  if (w) w->release(stream);
   std::lock_guard<std::mutex> lk(mu);
-  if (w) spare.push_back(std::move(w));
+  if (w) {
+    st.cached_bytes += w->held_bytes();
+    spare.push_back(std::move(w));
+  }
   r->status = e.ok() ? r->status : e.code;
   r->msg = e.ok() ? r->msg : e.msg;
   if (!e.ok() && r->p_dev) {
     dev_free(r->p_dev, stream);
     r->p_dev = nullptr;
   }
-  st.used_bytes -= r->reserve;
+  st.used_bytes -= r->accounted;
   r->held = r->p_dev ? size_t(r->n) * r->n * 8 : 0;
   st.used_bytes += r->held;
+  st.peak_used_bytes = std::max(st.peak_used_bytes, st.used_bytes + st.cached_bytes);
   st.active -= 1;
   st.completed += 1;
   if (!e.ok()) st.failed += 1;
@@ -572,15 +598,14 @@ void spamm_server::run() {
           int64_t load = 0;
           for (const Request* q : running) load += q->products;
           if (!queue.empty() && int64_t(running.size()) < opt.max_active &&
-              queue.front()->reserve <= budget - std::min(budget, size_t(st.used_bytes)) &&
               (opt.fill_products <= 0 || running.empty() || load < opt.fill_products)) {
-            r = queue.front();
-            queue.pop_front();
-            st.queued -= 1;
-            st.active += 1;
-            st.used_bytes += r->reserve;
-            st.peak_used_bytes = std::max(st.peak_used_bytes, st.used_bytes);
-            break;
+            if (!fits(queue.front()) && st.cached_bytes > 0) trim_cache();
+            if (fits(queue.front())) {
+              r = queue.front();
+              queue.pop_front();
+              admit(r);
+              break;
+            }
           }
           if (!running.empty()) break;
           cv_work.wait(lk);
@@ -891,6 +916,7 @@ void spamm_server_destroy(spamm_server* sv) {
     if (r->p_dev) dev_free(r->p_dev, sv->stream);
     delete r;
   }
+  for (auto& w : sv->spare) w->release(sv->stream);
   sv->spare.clear();
   (void)hipStreamSynchronize(sv->stream);
   (void)hipFree(sv->args_dev);

@@ -50,7 +50,7 @@ def test_struct_sizes_match_the_header():
     assert ctypes.sizeof(_lib.Sp2Stats) == 8 + 24 + 8 + 256 + 4 * 8 * 256
     assert ctypes.sizeof(_lib.Profile) == 6 * 8 * 2 + 8
     assert ctypes.sizeof(_lib.ServerOptions) == 16
-    assert ctypes.sizeof(_lib.ServerInfo) == 11 * 8
+    assert ctypes.sizeof(_lib.ServerInfo) == 12 * 8
 
 
 def test_server_options_defaults_and_host_side_argument_checks():

@@ -73,6 +73,7 @@ def test_mixed_requests_match_solo_solves_bitwise(sp, inputs, alone):
     assert info["submitted"] == info["completed"] == len(CASES)
     assert info["failed"] == 0 and info["queued"] == 0 and info["active"] == 0
     assert info["used_bytes"] == 0
+    assert info["used_bytes"] + info["cached_bytes"] <= info["budget_bytes"]
     # Batched: one leaf-product launch per precision and step, so fewer
     # launches than the requests' iterations added up.
     assert info["gemm_launches"] < info["solve_iterations"]
