@@ -12,8 +12,16 @@ Printed: one JSON line.  `value` is the SpAMM effective rate over the timed
 solves, 65,536 flop per executed 32x32x32 leaf product divided by wall time.
 Also reported: SP2 solves/s and p50/p99 solve latency, spamm_multiply of
 X_0 * X_0 at tau in {1e-8, 1e-6, 1e-4}, the roofline of the leaf-product
-kernel from HIP events recorded around each of its launches, and the FP64
+kernel from HIP events recorded around each of its launches, the serving
+stream (Poisson arrivals of mixed-size requests, solved one at a time with
+FP32 leaves and by the lockstep server with FP32 and with split FP16 hi+lo
+leaves: solves/s, p50/p99 latency, error against FP64 leaves), and the FP64
 oracle timed on the host cores on a bounded sample.
+
+Other configurations use the same line: --molecules 1000 [--decay 2.5] for
+the 1000-molecule system, --precision bf16|fp16|bf16x3|fp16x3 with
+--compare-fp64 for the reduced-precision forms, --serve-requests 256 for
+the full serving stream.
 """
 from __future__ import annotations
 
@@ -33,6 +41,7 @@ if ROOT not in sys.path:
 LEAF_FLOP = 2 * 32 ** 3            # one 32x32x32 leaf product
 PEAK_FP32_TFLOPS = 157.3           # MI355X dense FP32 matrix peak
 PEAK_FP64_TFLOPS = 78.6
+PEAK_16BIT_TFLOPS = 2500.0        # dense BF16 / FP16 matrix peak
 PEAK_HBM_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 GEMM_SOURCE = os.path.join(ROOT, "paper_1403_7458_amd", "csrc", "leafgemm.hip")
@@ -200,6 +209,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tau", type=float, default=1e-6)
     ap.add_argument("--molecules", type=int, default=150)
+    ap.add_argument("--decay", type=float, default=1.5)
+    ap.add_argument("--precision", default="fp32",
+                    choices=["fp64", "fp32", "bf16", "fp16", "bf16x3", "fp16x3"])
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="also solve with FP64 leaves and report the error against it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-multiply", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=64,
@@ -225,13 +239,13 @@ def main():
     sp.load()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
-    w = water_cluster(args.molecules, 1.5, 0)
-    n, n_occ, tau = w.n, w.n_occ, args.tau
+    w = water_cluster(args.molecules, args.decay, 0)
+    n, n_occ, tau, prec = w.n, w.n_occ, args.tau, args.precision
     f = torch.from_numpy(w.f).to(dev)
     p = torch.empty_like(f)
 
     def solve():
-        return sp.sp2_solve(f, n_occ, tau, out=p, precision="fp32", stream=stream)
+        return sp.sp2_solve(f, n_occ, tau, out=p, precision=prec, stream=stream)
 
     for _ in range(args.warmup):
         solve()
@@ -257,19 +271,33 @@ def main():
     tr_err = abs(float(torch.trace(pt)) - n_occ)
     idem = float(torch.linalg.norm(pt @ pt - pt))
 
+    accuracy = None
+    if args.compare_fp64:
+        p64 = torch.empty_like(f)
+        sp.sp2_solve(f, n_occ, tau, out=p64, precision="fp64", stream=stream)
+        torch.cuda.synchronize()
+        accuracy = {"rel_err_vs_fp64": float(torch.linalg.norm(p - p64) / torch.linalg.norm(p64)),
+                    "fp64_trace_error": abs(float(torch.trace(p64)) - n_occ),
+                    "fp64_idempotency": float(torch.linalg.norm(p64 @ p64 - p64))}
+        del p64
+
     # Roofline of the leaf-product kernel: algorithmic flop per launch over
-    # the mean launch duration from the events bracketing each launch.
+    # the mean launch duration from the events bracketing each launch.  The
+    # split forms run three MFMA products per leaf product.
     launches = prof["launches"]["gemm"]
     gemm_ms = prof["ms"]["gemm"] / max(launches, 1)
     per_launch = prof["gemm_products"] / max(launches, 1)
-    achieved = LEAF_FLOP * per_launch / (gemm_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": measured_traffic(
-                    "leaf_gemm_f32_" + os.environ.get("SPAMM_LEAF_KERNEL", "w2x2s"),
-                    f"water{args.molecules}_tau{tau:g}"),
-                "kernel": "k_leaf_gemm_f32 " + os.environ.get("SPAMM_LEAF_KERNEL", "w2x2s")
-                          + " (fused SP2 update)",
+    mfma_per_leaf = 3 if prec.endswith("x3") else 1
+    peak = {"fp64": PEAK_FP64_TFLOPS, "fp32": PEAK_FP32_TFLOPS}.get(prec, PEAK_16BIT_TFLOPS)
+    achieved = mfma_per_leaf * LEAF_FLOP * per_launch / (gemm_ms * 1e-3) / 1e12
+    choice = os.environ.get("SPAMM_LEAF_KERNEL", "w2x2s")
+    kname = {"fp64": "k_leaf_gemm_f64 (one wave per C block)",
+             "fp32": f"k_leaf_gemm_f32 {choice}"}.get(prec, f"k_leaf_gemm_half_w2x2<{prec}>")
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak,
+                "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic(f"leaf_gemm_{prec}_{choice}",
+                                            f"water{args.molecules}_decay{args.decay:g}_tau{tau:g}"),
+                "kernel": kname + " (fused SP2 update)",
                 "launches": launches, "mean_launch_ms": round(gemm_ms, 4),
                 "products_per_launch": round(per_launch, 1)}
     phase_ms = {k: round(v / args.steps, 3) for k, v in prof["ms"].items()}
@@ -277,7 +305,7 @@ def main():
     multiply = {}
     x0 = None
     if not args.no_multiply:
-        mx, lo, hi = sp.sp2_initial_guess(f, "fp32", stream=stream)
+        mx, lo, hi = sp.sp2_initial_guess(f, prec, stream=stream)
         for t in (1e-8, 1e-6, 1e-4):
             sp.spamm_multiply(mx, mx, t, stream=stream)
             times, st = [], None
@@ -327,18 +355,22 @@ def main():
         "metric": "SpAMM effective GFLOP/s & SP2 solves/sec at tau=1e-6; p50/p99 solve latency",
         "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16": "bf16", "fp16": "f16",
+                  "bf16x3": "bf16x3 (hi+lo, f32 accumulation)",
+                  "fp16x3": "f16x3 (hi+lo, f32 accumulation)"}[prec],
         "data": "synthetic",
         "config": {"workload": f"sp2_solve water cluster {args.molecules} molecules "
                                f"(N={n}, padded {32 * (1 << int(np.ceil(np.log2(n / 32))))}), "
-                               f"decay 1.5 A, seed 0, fp32 leaves, tau={tau:g}",
+                               f"decay {args.decay:g} A, seed 0, {prec} leaves, tau={tau:g}",
                    "molecules": args.molecules, "n": n, "n_occ": n_occ, "tau": tau,
-                   "leaf": 32, "precision": "fp32"},
+                   "decay": args.decay, "leaf": 32, "precision": prec},
         "sp2_solves_per_s": round(args.steps / elapsed, 3),
         "latency_ms": {"p50": round(percentile(lat, 50) * 1e3, 3),
                        "p99": round(percentile(lat, 99) * 1e3, 3)},
         "sp2": {"iterations": stats["iterations"], "stop": stats["stop"],
-                "leaf_products": execs, "trace_error": tr_err, "idempotency": idem},
+                "leaf_products": execs, "trace_error": tr_err, "idempotency": idem,
+                "accuracy": accuracy},
         "phase_ms_per_step": phase_ms,
         "multiply": multiply,
         "serving": serve,

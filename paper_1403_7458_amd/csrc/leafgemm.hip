@@ -392,6 +392,7 @@ __device__ inline void mma_w2x2(const W2x2Frag& f, int mask, v16f (&acc)[4]) {
 }
 
 constexpr int kWBatch = 32;            // list entries per slot batch (64 steps)
+constexpr int kW2x2Waves = 1;          // default waves per workgroup
 
 // kAhead: operand sets in flight per wave (2: the next step's loads overlap
 // the current step's products; 1: other waves hide the latency).
@@ -501,18 +502,19 @@ __device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
   emit(3, acc[3]);
 }
 
-template <int kAhead>
-__global__ void __launch_bounds__(256) k_leaf_gemm_f32_w2x2(GemmArgs g) {
-  __shared__ int32_t s_tab[kWaves][5][2 * kWBatch];
+// kW: waves (2 x 2 groups) per workgroup.
+template <int kAhead, int kW>
+__global__ void __launch_bounds__(64 * kW) k_leaf_gemm_f32_w2x2(GemmArgs g) {
+  __shared__ int32_t s_tab[kW][5][2 * kWBatch];
   const int wave = threadIdx.x >> 6;
-  const int64_t p = uniform(xcd_contiguous_block() * kWaves + wave);
+  const int64_t p = uniform(xcd_contiguous_block() * kW + wave);
   if (p >= g.n_super) return;
   f32_w2x2<kAhead>(g, p, threadIdx.x & 63, s_tab[wave]);
 }
 
-template <int kAhead>
-__global__ void __launch_bounds__(256) k_leaf_gemm_f32_w2x2_batch(GemmBatch b) {
-  __shared__ int32_t s_tab[kWaves][5][2 * kWBatch];
+template <int kAhead, int kW>
+__global__ void __launch_bounds__(64 * kW) k_leaf_gemm_f32_w2x2_batch(GemmBatch b) {
+  __shared__ int32_t s_tab[kW][5][2 * kWBatch];
   const int wave = threadIdx.x >> 6;
   int64_t p = 0;
   const GemmArgs* g = batch_locate(b, wave, p);
@@ -886,6 +888,45 @@ int leaf_kernel_choice() {
   return kLeafDefault;
 }
 
+// Waves per workgroup of the FP32 2 x 2 kernels (SPAMM_LEAF_WAVES: 1, 2 or
+// 4).  One wave per workgroup measured fastest: a workgroup's slot on a CU
+// is freed when its own group is done, not when the slowest of four is.
+static int leaf_waves_choice() {
+  const char* v = std::getenv("SPAMM_LEAF_WAVES");
+  if (v && std::strcmp(v, "2") == 0) return 2;
+  if (v && std::strcmp(v, "4") == 0) return 4;
+  return kW2x2Waves;
+}
+
+template <int kAhead>
+static void launch_w2x2_a(int waves, const GemmArgs& g, hipStream_t s) {
+  const unsigned grid = unsigned((g.n_super + waves - 1) / waves);
+  if (waves == 1)
+    k_leaf_gemm_f32_w2x2<kAhead, 1><<<grid, 64, 0, s>>>(g);
+  else if (waves == 2)
+    k_leaf_gemm_f32_w2x2<kAhead, 2><<<grid, 128, 0, s>>>(g);
+  else
+    k_leaf_gemm_f32_w2x2<kAhead, 4><<<grid, 256, 0, s>>>(g);
+}
+
+static void launch_w2x2(int ahead, int waves, const GemmArgs& g, hipStream_t s) {
+  if (ahead == 2)
+    launch_w2x2_a<2>(waves, g, s);
+  else
+    launch_w2x2_a<1>(waves, g, s);
+}
+
+template <int kAhead>
+static void launch_w2x2_batch_a(int waves, const GemmBatch& b, hipStream_t s) {
+  const unsigned grid = unsigned(b.first[b.n]);
+  if (waves == 1)
+    k_leaf_gemm_f32_w2x2_batch<kAhead, 1><<<grid, 64, 0, s>>>(b);
+  else if (waves == 2)
+    k_leaf_gemm_f32_w2x2_batch<kAhead, 2><<<grid, 128, 0, s>>>(b);
+  else
+    k_leaf_gemm_f32_w2x2_batch<kAhead, 4><<<grid, 256, 0, s>>>(b);
+}
+
 void launch_leaf_gemm(int prec, const GemmArgs& g, hipStream_t s) {
   if (g.n_nodes <= 0) return;
   if (prec != SPAMM_FP64 && prec != SPAMM_FP32) {
@@ -898,11 +939,7 @@ void launch_leaf_gemm(int prec, const GemmArgs& g, hipStream_t s) {
     return;
   }
   if (prec == SPAMM_FP32 && g.n_super > 0 && (choice == kLeafW2x2 || choice == kLeafW2x2s)) {
-    const unsigned grid = unsigned((g.n_super + kWaves - 1) / kWaves);
-    if (choice == kLeafW2x2)
-      k_leaf_gemm_f32_w2x2<2><<<grid, 256, 0, s>>>(g);
-    else
-      k_leaf_gemm_f32_w2x2<1><<<grid, 256, 0, s>>>(g);
+    launch_w2x2(choice == kLeafW2x2 ? 2 : 1, leaf_waves_choice(), g, s);
     return;
   }
   if (prec == SPAMM_FP32 && g.n_super > 0 && (choice == kLeaf2x2 || choice == kLeaf4x4)) {
@@ -931,12 +968,13 @@ void launch_leaf_gemm_batch(int prec, const GemmArgs* host, const GemmArgs* dev,
   auto grid = [](const GemmBatch& b) { return unsigned(b.first[b.n]); };
   // 2 x 2 groups (FP32 with a tier d-1 frontier).
   if (grouped) {
-    for_each_batch(dev, n, kWaves, [&](int r) { return host[r].n_nodes > 0 ? host[r].n_super : 0; },
+    const int waves = leaf_waves_choice();
+    for_each_batch(dev, n, waves, [&](int r) { return host[r].n_nodes > 0 ? host[r].n_super : 0; },
                    [&](const GemmBatch& b) {
                      if (choice == kLeafW2x2)
-                       k_leaf_gemm_f32_w2x2_batch<2><<<grid(b), 256, 0, s>>>(b);
+                       launch_w2x2_batch_a<2>(waves, b, s);
                      else
-                       k_leaf_gemm_f32_w2x2_batch<1><<<grid(b), 256, 0, s>>>(b);
+                       launch_w2x2_batch_a<1>(waves, b, s);
                    });
   }
   // One wave per C block: FP64, FP32 trees of one tier, FP32 "block".

@@ -14,6 +14,9 @@
 // Ownership and order are those of the FP32 kernels: one wave per 2 x 2
 // group of C blocks (or one per C block when the tree has one tier), each C
 // block accumulated over its own k in ascending order.
+#include <cstdlib>
+#include <cstring>
+
 #include "device_util.h"
 #include "half.h"
 #include "internal.h"
@@ -25,6 +28,7 @@ namespace {
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int kWaves = 4;
+constexpr int kHalfW2x2Waves = 1;  // default waves per workgroup of the 2 x 2 kernels
 constexpr int kWBatch = 32;  // list entries per slot batch (64 steps)
 
 template <int P>
@@ -227,18 +231,19 @@ __device__ __forceinline__ void half_w2x2(const GemmArgs& g, int64_t p, int lane
   }
 }
 
-template <int P>
-__global__ void __launch_bounds__(256) k_leaf_gemm_half_w2x2(GemmArgs g) {
-  __shared__ int32_t s_tab[kWaves][5][2 * kWBatch];
+// kW: waves (2 x 2 groups) per workgroup.
+template <int P, int kW>
+__global__ void __launch_bounds__(64 * kW) k_leaf_gemm_half_w2x2(GemmArgs g) {
+  __shared__ int32_t s_tab[kW][5][2 * kWBatch];
   const int wave = threadIdx.x >> 6;
-  const int64_t p = uniform(xcd_contiguous_block() * kWaves + wave);
+  const int64_t p = uniform(xcd_contiguous_block() * kW + wave);
   if (p >= g.n_super) return;
   half_w2x2<P>(g, p, threadIdx.x & 63, s_tab[wave]);
 }
 
-template <int P>
-__global__ void __launch_bounds__(256) k_leaf_gemm_half_w2x2_batch(GemmBatch b) {
-  __shared__ int32_t s_tab[kWaves][5][2 * kWBatch];
+template <int P, int kW>
+__global__ void __launch_bounds__(64 * kW) k_leaf_gemm_half_w2x2_batch(GemmBatch b) {
+  __shared__ int32_t s_tab[kW][5][2 * kWBatch];
   const int wave = threadIdx.x >> 6;
   int64_t p = 0;
   const GemmArgs* g = batch_locate(b, wave, p);
@@ -336,10 +341,24 @@ __global__ void __launch_bounds__(256) k_sp2_rest_half(RestArgs r) {
   }
 }
 
+// Waves per workgroup of the 2 x 2 kernels (SPAMM_LEAF_WAVES: 1, 2 or 4).
+static int half_waves() {
+  const char* v = std::getenv("SPAMM_LEAF_WAVES");
+  if (v && std::strcmp(v, "2") == 0) return 2;
+  if (v && std::strcmp(v, "4") == 0) return 4;
+  return kHalfW2x2Waves;
+}
+
 template <int P>
 void launch_p(const GemmArgs& g, hipStream_t s) {
-  if (g.n_super > 0)
-    k_leaf_gemm_half_w2x2<P><<<unsigned((g.n_super + kWaves - 1) / kWaves), 256, 0, s>>>(g);
+  const int w = half_waves();
+  const unsigned gw = unsigned((g.n_super + w - 1) / w);
+  if (g.n_super > 0 && w == 1)
+    k_leaf_gemm_half_w2x2<P, 1><<<gw, 64, 0, s>>>(g);
+  else if (g.n_super > 0 && w == 2)
+    k_leaf_gemm_half_w2x2<P, 2><<<gw, 128, 0, s>>>(g);
+  else if (g.n_super > 0)
+    k_leaf_gemm_half_w2x2<P, 4><<<gw, 256, 0, s>>>(g);
   else
     k_leaf_gemm_half_block<P><<<unsigned((g.n_nodes + kWaves - 1) / kWaves), 256, 0, s>>>(g);
 }
@@ -347,8 +366,16 @@ void launch_p(const GemmArgs& g, hipStream_t s) {
 template <int P>
 void launch_batch_p(const GemmArgs* host, const GemmArgs* dev, int n, hipStream_t s) {
   auto grid = [](const GemmBatch& b) { return unsigned(b.first[b.n]); };
-  for_each_batch(dev, n, kWaves, [&](int r) { return host[r].n_nodes > 0 ? host[r].n_super : 0; },
-                 [&](const GemmBatch& b) { k_leaf_gemm_half_w2x2_batch<P><<<grid(b), 256, 0, s>>>(b); });
+  const int w = half_waves();
+  for_each_batch(dev, n, w, [&](int r) { return host[r].n_nodes > 0 ? host[r].n_super : 0; },
+                 [&](const GemmBatch& b) {
+                   if (w == 1)
+                     k_leaf_gemm_half_w2x2_batch<P, 1><<<grid(b), 64, 0, s>>>(b);
+                   else if (w == 2)
+                     k_leaf_gemm_half_w2x2_batch<P, 2><<<grid(b), 128, 0, s>>>(b);
+                   else
+                     k_leaf_gemm_half_w2x2_batch<P, 4><<<grid(b), 256, 0, s>>>(b);
+                 });
   for_each_batch(dev, n, kWaves, [&](int r) { return host[r].n_super > 0 ? 0 : host[r].n_nodes; },
                  [&](const GemmBatch& b) { k_leaf_gemm_half_block_batch<P><<<grid(b), 256, 0, s>>>(b); });
 }
