@@ -173,6 +173,7 @@ __device__ inline void write_parent(const TierIn& in, const double* na, const do
 
 struct TopArgs {
   int depth, t0;
+  int want_err;  // also the culled-product bound of tiers 1..t0
   double tau;
   const double* norms_a;
   const double* norms_b;
@@ -247,9 +248,11 @@ __global__ void __launch_bounds__(kTopThreads) k_cull_top(TopArgs g) {
     s_wc[wave] = ic;
     s_wz[wave] = iz;
   }
-  // Culled-product bound of tiers 1..t0, summed per thread in a fixed order.
+  // Culled-product bound of tiers 1..t0, summed per thread in a fixed order
+  // (only when asked for: SP2 never reads it, and it is most of this
+  // kernel's time).
   double e = 0.0;
-  for (int t = 1; t <= t0; ++t) {
+  for (int t = 1; g.want_err && t <= t0; ++t) {
     const int w = 1 << t;
     const double* a = sa + tier_offset(t);
     const double* b = sb + tier_offset(t);
@@ -572,10 +575,11 @@ void expand(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, int t, do
 }
 
 void launch_top(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, int t0, double tau,
-                hipStream_t s) {
+                bool want_err, hipStream_t s) {
   TopArgs g{};
   g.depth = a->depth;
   g.t0 = t0;
+  g.want_err = want_err ? 1 : 0;
   g.tau = tau;
   g.norms_a = a->norms;
   g.norms_b = b->norms;
@@ -642,7 +646,7 @@ Error cull_launch(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, dou
   Control* ctl = w.ctl_dev;
   {
     PhaseTimer timer(SPAMM_PHASE_CULL, s);
-    launch_top(w, a, b, t_top, tau, s);
+    launch_top(w, a, b, t_top, tau, want_pairs, s);
     for (int t = t_top; t < d; ++t) expand(w, a, b, t, tau, s);
     if (want_pairs)
       k_nonzero_pairs<<<1, 1024, 0, s>>>(a->norms + tier_offset(d), b->norms + tier_offset(d),

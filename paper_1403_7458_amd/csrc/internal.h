@@ -236,7 +236,8 @@ struct CullResult {
 
 // Runs the occlusion pass tier by tier and synchronises `s` once (plus once
 // per regrowth of the frontier buffers).  With want_pairs the count of
-// non-zero block pairs is computed too.
+// non-zero block pairs and the complete culled-product bound (err_bound)
+// are computed too; without, err_bound misses the top tiers.
 Error run_cull(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
                bool want_pairs, hipStream_t s, CullResult* out);
 // The same in two halves: cull_launch queues the pass and the copy of the
