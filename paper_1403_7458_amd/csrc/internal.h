@@ -309,6 +309,9 @@ struct GemmArgs {
 enum { kLeafBlock = 0, kLeaf2x2 = 1, kLeaf4x4 = 2, kLeafW2x2 = 3, kLeafW2x2s = 4,
        kLeafDefault = kLeafW2x2s };
 int leaf_kernel_choice();
+// Waves per workgroup of the 2 x 2 kernels for a launch of `groups` groups.
+constexpr int64_t kManyGroups = 16384;
+int w2x2_waves(int64_t groups);
 void launch_leaf_gemm(int prec, const GemmArgs& g, hipStream_t s);
 // 16-bit forms (leafgemm16.hip).
 void launch_leaf_gemm_half(int prec, const GemmArgs& g, hipStream_t s);

@@ -392,7 +392,6 @@ __device__ inline void mma_w2x2(const W2x2Frag& f, int mask, v16f (&acc)[4]) {
 }
 
 constexpr int kWBatch = 32;            // list entries per slot batch (64 steps)
-constexpr int kW2x2Waves = 1;          // default waves per workgroup
 
 // kAhead: operand sets in flight per wave (2: the next step's loads overlap
 // the current step's products; 1: other waves hide the latency).
@@ -888,14 +887,19 @@ int leaf_kernel_choice() {
   return kLeafDefault;
 }
 
-// Waves per workgroup of the FP32 2 x 2 kernels (SPAMM_LEAF_WAVES: 1, 2 or
-// 4).  One wave per workgroup measured fastest: a workgroup's slot on a CU
-// is freed when its own group is done, not when the slowest of four is.
-static int leaf_waves_choice() {
+// Waves (2 x 2 groups) per workgroup of the 2 x 2 kernels for a launch of
+// `groups` groups (SPAMM_LEAF_WAVES = 1, 2 or 4 overrides).  Measured: with
+// a few thousand groups (150 molecules: 3,481) one wave per workgroup is
+// fastest, since a workgroup's CU slot is freed when its own group is done
+// rather than when the slowest of four is (+4%); with 10^5 groups (1000
+// molecules: 152,881) four neighbouring groups per workgroup share the CU's
+// L1 and are faster (+4% FP32, +7% split FP16).
+int w2x2_waves(int64_t groups) {
   const char* v = std::getenv("SPAMM_LEAF_WAVES");
+  if (v && std::strcmp(v, "1") == 0) return 1;
   if (v && std::strcmp(v, "2") == 0) return 2;
   if (v && std::strcmp(v, "4") == 0) return 4;
-  return kW2x2Waves;
+  return groups >= kManyGroups ? 4 : 1;
 }
 
 template <int kAhead>
@@ -939,7 +943,7 @@ void launch_leaf_gemm(int prec, const GemmArgs& g, hipStream_t s) {
     return;
   }
   if (prec == SPAMM_FP32 && g.n_super > 0 && (choice == kLeafW2x2 || choice == kLeafW2x2s)) {
-    launch_w2x2(choice == kLeafW2x2 ? 2 : 1, leaf_waves_choice(), g, s);
+    launch_w2x2(choice == kLeafW2x2 ? 2 : 1, w2x2_waves(g.n_super), g, s);
     return;
   }
   if (prec == SPAMM_FP32 && g.n_super > 0 && (choice == kLeaf2x2 || choice == kLeaf4x4)) {
@@ -968,7 +972,9 @@ void launch_leaf_gemm_batch(int prec, const GemmArgs* host, const GemmArgs* dev,
   auto grid = [](const GemmBatch& b) { return unsigned(b.first[b.n]); };
   // 2 x 2 groups (FP32 with a tier d-1 frontier).
   if (grouped) {
-    const int waves = leaf_waves_choice();
+    int64_t groups = 0;
+    for (int r = 0; r < n; ++r) groups += host[r].n_nodes > 0 ? host[r].n_super : 0;
+    const int waves = w2x2_waves(groups);
     for_each_batch(dev, n, waves, [&](int r) { return host[r].n_nodes > 0 ? host[r].n_super : 0; },
                    [&](const GemmBatch& b) {
                      if (choice == kLeafW2x2)

@@ -28,7 +28,6 @@ namespace {
 typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int kWaves = 4;
-constexpr int kHalfW2x2Waves = 1;  // default waves per workgroup of the 2 x 2 kernels
 constexpr int kWBatch = 32;  // list entries per slot batch (64 steps)
 
 template <int P>
@@ -341,17 +340,9 @@ __global__ void __launch_bounds__(256) k_sp2_rest_half(RestArgs r) {
   }
 }
 
-// Waves per workgroup of the 2 x 2 kernels (SPAMM_LEAF_WAVES: 1, 2 or 4).
-static int half_waves() {
-  const char* v = std::getenv("SPAMM_LEAF_WAVES");
-  if (v && std::strcmp(v, "2") == 0) return 2;
-  if (v && std::strcmp(v, "4") == 0) return 4;
-  return kHalfW2x2Waves;
-}
-
 template <int P>
 void launch_p(const GemmArgs& g, hipStream_t s) {
-  const int w = half_waves();
+  const int w = w2x2_waves(g.n_super);
   const unsigned gw = unsigned((g.n_super + w - 1) / w);
   if (g.n_super > 0 && w == 1)
     k_leaf_gemm_half_w2x2<P, 1><<<gw, 64, 0, s>>>(g);
@@ -366,7 +357,9 @@ void launch_p(const GemmArgs& g, hipStream_t s) {
 template <int P>
 void launch_batch_p(const GemmArgs* host, const GemmArgs* dev, int n, hipStream_t s) {
   auto grid = [](const GemmBatch& b) { return unsigned(b.first[b.n]); };
-  const int w = half_waves();
+  int64_t groups = 0;
+  for (int r = 0; r < n; ++r) groups += host[r].n_nodes > 0 ? host[r].n_super : 0;
+  const int w = w2x2_waves(groups);
   for_each_batch(dev, n, w, [&](int r) { return host[r].n_nodes > 0 ? host[r].n_super : 0; },
                  [&](const GemmBatch& b) {
                    if (w == 1)

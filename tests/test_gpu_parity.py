@@ -21,7 +21,7 @@ from oracle import alg1
 from oracle import sp2_oracle as sp2o
 from oracle import spamm_oracle as so
 from watergen import synthetic as syn
-from watergen import water_cluster
+from watergen import water_cluster, water_cluster_torch
 
 pytestmark = pytest.mark.gpu
 
@@ -348,6 +348,62 @@ def test_spamm_multiply_c2_sampled(torch_dev, lib):
                 ks = so.executed_ks(na, na, tau, i, j)
                 scale = float((na[i, ks] * na[ks, j]).sum())
                 assert np.linalg.norm(g - o) <= 1e-5 * scale + 1e-30
+
+
+@pytest.mark.slow
+def test_spamm_multiply_c3_sampled(torch_dev, lib):
+    """1000 molecules, N = 25000 -> 32768 (nb 1024, depth 10), FP32 leaves:
+    the Gershgorin bounds, the executed-task count of X_0 * X_0 at tau 1e-6
+    and sampled C blocks against the oracle, at the full size."""
+    torch, dev = torch_dev
+    f_dev, n_occ = water_cluster_torch(1000, 1.5, 0, device=dev)
+    n = f_dev.shape[0]
+    mx, glo, ghi = lib.sp2_initial_guess(f_dev, "fp32")
+    f = f_dev.cpu().numpy()
+    lo, hi = sp2o.gershgorin(f)
+    assert glo == pytest.approx(lo, rel=1e-13) and ghi == pytest.approx(hi, rel=1e-13)
+    x0 = sp2o.initial_x(f, lo, hi, 32768)
+    del f
+    na = so.leaf_norms(x0)
+    tau = 1e-6
+    mc, st = lib.spamm_multiply(mx, mx, tau)
+    keep = tie = 0
+    for i in range(na.shape[0]):                      # the flat test, row by row
+        prod = na[i, None, :] * na.T
+        keep += int((prod > tau).sum())
+        tie += int((np.abs(prod - tau) <= TIE * tau).sum())
+    assert abs(st["n_exec"] - keep) <= tie
+    assert st["n_dense"] == 1024 ** 3
+    c = torch.empty((n, n), dtype=torch.float64, device=dev)
+    lib.spamm_to_dense(mc, out=c)
+    rng = np.random.Generator(np.random.PCG64(1))
+    rows = sorted(set(rng.integers(0, 782, 4).tolist()) | {0, 781})
+    cols = sorted(set(rng.integers(0, 782, 4).tolist()) | {390})
+    cref, _ = so.spamm(x0, x0, tau, rows=rows, cols=cols)
+    for i in rows:
+        for j in cols:
+            g = c[i * 32:(i + 1) * 32, j * 32:(j + 1) * 32].cpu().numpy()
+            o = cref[i * 32:(i + 1) * 32, j * 32:(j + 1) * 32][:g.shape[0], :g.shape[1]]
+            ks = so.executed_ks(na, na, tau, i, j)
+            scale = float((na[i, ks] * na[ks, j]).sum())
+            assert np.linalg.norm(g - o) <= 1e-5 * scale + 1e-30
+
+
+@pytest.mark.slow
+def test_sp2_c3_full_size_properties(torch_dev, lib):
+    """1000-molecule SP2 with FP32 leaves at tau 1e-6: stops on the stall
+    rule below its floor, and P is symmetric, has trace n_occ and is
+    idempotent to the FP32 floor (properties that hold at any size; the
+    oracle is checked on the same system block by block above)."""
+    torch, dev = torch_dev
+    f_dev, n_occ = water_cluster_torch(1000, 1.5, 0, device=dev)
+    p = torch.empty_like(f_dev)
+    _, st = lib.sp2_solve(f_dev, n_occ, 1e-6, out=p, precision="fp32")
+    floor = 1e-3 * np.sqrt(n_occ)
+    assert st["stop"] in ("converged", "stalled") and st["errors"][-1] < floor
+    assert float(torch.linalg.norm(p - p.T)) <= 1e-4 * float(torch.linalg.norm(p))
+    assert abs(float(torch.trace(p)) - n_occ) <= 0.1
+    assert float(torch.linalg.norm(p @ p - p)) <= floor
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
