@@ -271,6 +271,14 @@ def main():
     tr_err = abs(float(torch.trace(pt)) - n_occ)
     idem = float(torch.linalg.norm(pt @ pt - pt))
 
+    # The same solve with full squares (untimed): the leaf products the
+    # plain method executes, for the full-square-equivalent rate.
+    full_products = execs
+    if stats.get("symmetric"):
+        _, sfull = sp.sp2_solve(f, n_occ, tau, out=torch.empty_like(f), precision=prec,
+                                stream=stream, symmetric=False)
+        full_products = sfull["n_exec_total"]
+
     accuracy = None
     if args.compare_fp64:
         p64 = torch.empty_like(f)
@@ -369,8 +377,11 @@ def main():
         "latency_ms": {"p50": round(percentile(lat, 50) * 1e3, 3),
                        "p99": round(percentile(lat, 99) * 1e3, 3)},
         "sp2": {"iterations": stats["iterations"], "stop": stats["stop"],
-                "leaf_products": execs, "trace_error": tr_err, "idempotency": idem,
-                "accuracy": accuracy},
+                "symmetric_squares": bool(stats.get("symmetric")),
+                "leaf_products": execs, "leaf_products_full_squares": full_products,
+                "full_square_equivalent_gflops": round(
+                    LEAF_FLOP * full_products * args.steps / elapsed / 1e9, 1),
+                "trace_error": tr_err, "idempotency": idem, "accuracy": accuracy},
         "phase_ms_per_step": phase_ms,
         "multiply": multiply,
         "serving": serve,

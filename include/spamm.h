@@ -109,6 +109,12 @@ typedef struct sp2_options {
     double stall_floor;  /* default 0: max(1e-3, 4 u), u the leaf precision's unit
                             roundoff (FP64 2^-53, FP32 2^-24, BF16 2^-8, FP16 2^-11,
                             BF16X3 2^-16, FP16X3 2^-22) */
+    int32_t symmetric;   /* 1 (default): when F is exactly symmetric, every X_n is
+                            too, so each square computes only the C blocks (i, j)
+                            with i <= j (the products of E(tau) with i <= j; the
+                            task set of (j, i) is the same) and stores (j, i) as
+                            the transpose; 0: all C blocks */
+    int32_t reserved;
 } sp2_options;
 
 enum { SP2_STOP_CONVERGED = 0, SP2_STOP_STALLED = 1, SP2_STOP_MAX_ITER = 2 };
@@ -116,13 +122,16 @@ enum { SP2_STOP_CONVERGED = 0, SP2_STOP_STALLED = 1, SP2_STOP_MAX_ITER = 2 };
 typedef struct sp2_stats {
     int32_t iterations;               /* products computed */
     int32_t stop_reason;              /* SP2_STOP_* */
+    int32_t symmetric;                /* 1: upper-triangle squares (see sp2_options) */
+    int32_t reserved;
     double eps_min, eps_max;          /* Gershgorin bounds of F */
     double trace_final;               /* tr P */
     int64_t n_exec_total;             /* leaf products over all iterations */
     int8_t branch[SP2_MAX_ITER];      /* 1: X <- X^2, 0: X <- 2X - X^2 */
     double trace[SP2_MAX_ITER];       /* t_n = tr X_n */
     double err[SP2_MAX_ITER];         /* e_n = ||X~_n^2 - X_n||_F */
-    int64_t n_exec[SP2_MAX_ITER];     /* executed leaf products of iteration n */
+    int64_t n_exec[SP2_MAX_ITER];     /* executed leaf products of iteration n
+                                         (upper-triangle C blocks when symmetric) */
     int64_t n_blocks[SP2_MAX_ITER];   /* stored blocks of X_n */
 } sp2_stats;
 

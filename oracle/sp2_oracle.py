@@ -51,6 +51,7 @@ class SP2Result:
     traces: list                  # t_n = tr X_n
     errors: list                  # e_n = ||X~_n^2 - X_n||_F
     n_exec: list                  # executed leaf products per iteration
+    n_exec_upper: list            # the same, C blocks with i <= j only
     eps_min: float
     eps_max: float
     stop: int
@@ -91,7 +92,7 @@ def sp2(f: np.ndarray, n_occ: int, tau: float, tol: float = 1e-8, max_iter: int 
         raise ValueError("degenerate spectrum bounds")
     x = initial_x(f, eps_min, eps_max, n_pad)
     floor = stall_floor * math.sqrt(max(n_occ, 1))
-    branches, traces, errors, execs = [], [], [], []
+    branches, traces, errors, execs, uppers = [], [], [], [], []
     stop = STOP_MAX_ITER
     it = 0
     for it in range(max_iter):
@@ -104,6 +105,7 @@ def sp2(f: np.ndarray, n_occ: int, tau: float, tol: float = 1e-8, max_iter: int 
         traces.append(t)
         errors.append(e)
         execs.append(int(info["n_exec"]))
+        uppers.append(int(info.get("n_exec_upper", -1)))
         if it + 1 >= min_iter:
             if e < tol:
                 stop = STOP_CONVERGED
@@ -112,7 +114,8 @@ def sp2(f: np.ndarray, n_occ: int, tau: float, tol: float = 1e-8, max_iter: int 
                 stop = STOP_STALLED
                 break
     return SP2Result(p=x[:n, :n].copy(), iterations=it + 1, branches=branches, traces=traces,
-                     errors=errors, n_exec=execs, eps_min=eps_min, eps_max=eps_max, stop=stop)
+                     errors=errors, n_exec=execs, n_exec_upper=uppers, eps_min=eps_min,
+                     eps_max=eps_max, stop=stop)
 
 
 def energy_error(f: np.ndarray, p_ref: np.ndarray, p: np.ndarray) -> float:

@@ -123,7 +123,9 @@ def spamm(a: np.ndarray, b: np.ndarray, tau: float, n_pad: int | None = None,
     rows/cols: optional iterables of block indices restricting which C
     blocks are formed (for sampling large cases); other blocks stay zero.
     Returns (c_pad, info) with c_pad the padded product and info holding the
-    executed-task count and the leaf norms.
+    executed-task count, the count restricted to the C blocks with i <= j
+    (what a product known to be symmetric has to execute), and the leaf
+    norms.
     """
     tau = check_tau(tau)
     if a.shape != b.shape:
@@ -136,7 +138,7 @@ def spamm(a: np.ndarray, b: np.ndarray, tau: float, n_pad: int | None = None,
     nb = n_pad // LEAF
     c = np.zeros((n_pad, n_pad), dtype=np.float64)
     cb = blocks(c)
-    n_exec = 0
+    n_exec = n_exec_upper = 0
     rows = range(nb) if rows is None else rows
     cols = list(range(nb)) if cols is None else list(cols)
     for i in rows:
@@ -149,7 +151,9 @@ def spamm(a: np.ndarray, b: np.ndarray, tau: float, n_pad: int | None = None,
                 acc += ab[i, k] @ bb[k, j]
             cb[i, j] = acc
             n_exec += int(ks.size)
-    return c, {"n_exec": n_exec, "norms_a": na, "norms_b": nbn}
+            if i <= j:
+                n_exec_upper += int(ks.size)
+    return c, {"n_exec": n_exec, "n_exec_upper": n_exec_upper, "norms_a": na, "norms_b": nbn}
 
 
 def executed_set_breadth_first(tiers_a: list[np.ndarray], tiers_b: list[np.ndarray],

@@ -52,11 +52,13 @@ class MultStats(ctypes.Structure):
 class Sp2Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("min_iter", ctypes.c_int32), ("stall_rule", ctypes.c_int32),
-                ("tol", ctypes.c_double), ("stall_floor", ctypes.c_double)]
+                ("tol", ctypes.c_double), ("stall_floor", ctypes.c_double),
+                ("symmetric", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Sp2Stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("stop_reason", ctypes.c_int32),
+                ("symmetric", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("eps_min", ctypes.c_double), ("eps_max", ctypes.c_double),
                 ("trace_final", ctypes.c_double), ("n_exec_total", ctypes.c_int64),
                 ("branch", ctypes.c_int8 * SP2_MAX_ITER),
@@ -286,12 +288,13 @@ def spamm_matrix_norms(m: SpammMatrix, stream=None) -> list:
 
 
 def sp2_options(precision="fp32", max_iter=100, min_iter=0, stall_rule=True, tol=1e-8,
-                stall_floor=0.0) -> Sp2Options:
+                stall_floor=0.0, symmetric=True) -> Sp2Options:
     o = Sp2Options()
     load().sp2_options_default(ctypes.byref(o))
     o.precision = PRECISIONS.get(precision, precision)
     o.max_iter, o.min_iter, o.stall_rule = int(max_iter), int(min_iter), int(bool(stall_rule))
     o.tol, o.stall_floor = float(tol), float(stall_floor)
+    o.symmetric = int(bool(symmetric))
     return o
 
 
@@ -316,6 +319,7 @@ def _sp2_stats(rc: int, st: Sp2Stats) -> dict:
     it = st.iterations
     return {
         "status": rc, "iterations": it, "stop": STOP_REASONS[st.stop_reason],
+        "symmetric": bool(st.symmetric),
         "eps_min": st.eps_min, "eps_max": st.eps_max, "trace_final": st.trace_final,
         "n_exec_total": st.n_exec_total,
         "branches": [int(x) for x in st.branch[:it]],

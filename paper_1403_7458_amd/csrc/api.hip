@@ -372,6 +372,8 @@ void sp2_options_default(sp2_options* o) {
   o->stall_rule = 1;
   o->tol = 1e-8;
   o->stall_floor = 0.0;
+  o->symmetric = 1;
+  o->reserved = 0;
 }
 
 const char* spamm_last_error(void) { return g_last_error.c_str(); }

@@ -40,6 +40,7 @@ struct TierIn {
   const int64_t* nptr;
   const int32_t* ks;
   int64_t cap_nodes, cap_tasks;
+  int upper;  // keep only C nodes with I <= J (symmetric products)
 };
 
 struct TierOut {
@@ -63,9 +64,12 @@ __device__ inline int64_t wave_incl_scan(int64_t v, int lane) {
 }
 
 // Pass bits of the 8 children of (I, J, K): bit (q * 2 + c), q = 2a + b.
-// *culled gets the sum of the failing norm products.
+// *culled gets the sum of the failing norm products.  With `upper`, the
+// child (2I + 1, 2J) of a diagonal node lies below the diagonal: it is
+// neither executed nor culled (its block is the mirror of an upper one).
 __device__ inline uint32_t child_bits(const double* __restrict__ na, const double* __restrict__ nb,
-                                      int64_t w, int I, int J, int K, double tau, double* culled) {
+                                      int64_t w, int I, int J, int K, double tau, double* culled,
+                                      bool upper) {
   double av[2][2], bv[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -83,6 +87,7 @@ __device__ inline uint32_t child_bits(const double* __restrict__ na, const doubl
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
+        if (upper && I == J && a == 1 && b == 0) continue;
         const double p = av[a][c] * bv[c][b];
         if (p > tau)
           bits |= 1u << ((2 * a + b) * 2 + c);
@@ -108,7 +113,7 @@ __device__ inline void count_parent(const TierIn& in, const double* na, const do
     uint32_t bits = 0;
     if (x < end) {
       double ce;
-      bits = child_bits(na, nb, w, I, J, in.ks[x], tau, &ce);
+      bits = child_bits(na, nb, w, I, J, in.ks[x], tau, &ce, in.upper);
       e += ce;
       if (bits_out) bits_out[x] = uint8_t(bits);
     }
@@ -146,7 +151,7 @@ __device__ inline void write_parent(const TierIn& in, const double* na, const do
     if (x < end) {
       double ce;
       K = in.ks[x];
-      bits = child_bits(na, nb, w, I, J, K, tau, &ce);
+      bits = child_bits(na, nb, w, I, J, K, tau, &ce, in.upper);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -174,6 +179,7 @@ __device__ inline void write_parent(const TierIn& in, const double* na, const do
 struct TopArgs {
   int depth, t0;
   int want_err;  // also the culled-product bound of tiers 1..t0
+  int upper;     // only C nodes with I <= J
   double tau;
   const double* norms_a;
   const double* norms_b;
@@ -239,8 +245,9 @@ __global__ void __launch_bounds__(kTopThreads) k_cull_top(TopArgs g) {
   uint32_t mask = 0;
   if (tid < W * W) {
     demorton(tid, t0, &I, &J);
-    for (int K = 0; K < W; ++K)
-      if (A[I * W + K] * B[K * W + J] > g.tau) mask |= 1u << K;
+    if (!(g.upper && I > J))
+      for (int K = 0; K < W; ++K)
+        if (A[I * W + K] * B[K * W + J] > g.tau) mask |= 1u << K;
   }
   const int v = __popc(mask);
   const int64_t ic = wave_incl_scan(v, lane), iz = wave_incl_scan(v > 0 ? 1 : 0, lane);
@@ -260,6 +267,7 @@ __global__ void __launch_bounds__(kTopThreads) k_cull_top(TopArgs g) {
     const double* bp = sb + tier_offset(t - 1);
     for (int x = tid; x < w * w * w; x += kTopThreads) {
       const int i = x >> (2 * t), j = (x >> t) & (w - 1), k = x & (w - 1);
+      if (g.upper && i > j) continue;
       const double p = a[i * w + k] * b[k * w + j];
       if (p > g.tau) continue;
       if (t > 1 && !(ap[(i / 2) * (w / 2) + k / 2] * bp[(k / 2) * (w / 2) + j / 2] > g.tau))
@@ -547,7 +555,8 @@ Error reserve_tier(CullWork& w, int t, hipStream_t s) {
 
 TierIn tier_in(CullWork& w, int t) {
   return TierIn{static_cast<const int32_t*>(w.nodes[t].p), static_cast<const int64_t*>(w.nptr[t].p),
-                static_cast<const int32_t*>(w.ks[t].p), w.cap_nodes[t], w.cap_tasks[t]};
+                static_cast<const int32_t*>(w.ks[t].p), w.cap_nodes[t], w.cap_tasks[t],
+                w.upper ? 1 : 0};
 }
 
 TierOut tier_out(CullWork& w, int t) {
@@ -580,6 +589,7 @@ void launch_top(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, int t
   g.depth = a->depth;
   g.t0 = t0;
   g.want_err = want_err ? 1 : 0;
+  g.upper = w.upper ? 1 : 0;
   g.tau = tau;
   g.norms_a = a->norms;
   g.norms_b = b->norms;
@@ -608,6 +618,9 @@ void CullWork::release(hipStream_t s) {
   cnt4.release(s);
   bits.release(s);
   quad.release(s);
+  mflag.release(s);
+  moff.release(s);
+  mscan.part.release(s);
   toff.release(s);
   noff.release(s);
   part.release(s);
@@ -623,8 +636,9 @@ CullWork::~CullWork() {
 }
 
 Error cull_launch(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
-                  bool want_pairs, hipStream_t s) {
+                  bool want_pairs, hipStream_t s, bool upper) {
   const int d = a->depth;
+  w.upper = upper;
   const int t_top = std::min(d, kTopTier);
   SPAMM_TRY(ensure_control(w));
   if (w.depth != d) {
@@ -723,12 +737,33 @@ void launch_quad_masks(const CullResult& r, const spamm_matrix* a, const spamm_m
                        double tau, hipStream_t s) {
   if (r.n_quad <= 0) return;
   const int d = a->depth;
-  TierIn in{r.quad_nodes, r.quad_nptr, r.quad_ks, 0, 0};
+  TierIn in{r.quad_nodes, r.quad_nptr, r.quad_ks, 0, 0, 0};
   const unsigned grid = unsigned(std::min<int64_t>((r.n_quad + kWaves - 1) / kWaves, 8192));
   k_quad_masks<<<grid, 64 * kWaves, 0, s>>>(in, a->norms + tier_offset(d - 1),
                                             b->norms + tier_offset(d - 1), a->norms + tier_offset(d),
                                             b->norms + tier_offset(d), d, tau, r.n_quad,
                                             r.quad_masks);
+}
+
+namespace {
+
+__global__ void k_offdiag_flags(const int32_t* __restrict__ nodes, int64_t n,
+                                int32_t* __restrict__ flag) {
+  const int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (x < n) flag[x] = unpack_i(nodes[x]) != unpack_j(nodes[x]) ? 1 : 0;
+}
+
+}  // namespace
+
+Error launch_mirror_offsets(CullWork& w, const CullResult& r, int64_t* total_dev, hipStream_t s) {
+  const int64_t n = std::max<int64_t>(r.n_cblocks, 1);
+  SPAMM_TRY(w.mflag.grow(size_t(n) * sizeof(int32_t), s));
+  SPAMM_TRY(w.moff.grow(size_t(n) * sizeof(int64_t), s));
+  int32_t* flag = static_cast<int32_t*>(w.mflag.p);
+  if (r.n_cblocks > 0)
+    k_offdiag_flags<<<unsigned((r.n_cblocks + 255) / 256), 256, 0, s>>>(r.nodes, r.n_cblocks, flag);
+  return launch_scan(flag, static_cast<int64_t*>(w.moff.p), nullptr, nullptr, nullptr, 0, 1,
+                     r.n_cblocks, total_dev, nullptr, nullptr, w.mscan, s);
 }
 
 void launch_scatter_nodes(const int32_t* nodes, int64_t n, int nb, int32_t* map_c,
@@ -739,7 +774,7 @@ void launch_scatter_nodes(const int32_t* nodes, int64_t n, int nb, int32_t* map_
 
 Error run_cull(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
                bool want_pairs, hipStream_t s, CullResult* out) {
-  SPAMM_TRY(cull_launch(w, a, b, tau, want_pairs, s));
+  SPAMM_TRY(cull_launch(w, a, b, tau, want_pairs, s, false));
   SPAMM_HIP(hipStreamSynchronize(s));
   return cull_finish(w, a, b, tau, want_pairs, s, out);
 }

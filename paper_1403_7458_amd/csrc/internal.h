@@ -193,12 +193,16 @@ struct CullWork {
   int64_t cap_tasks[kMaxTiers] = {};
   DevBuf nodes[kMaxTiers], nptr[kMaxTiers], ks[kMaxTiers];
   DevBuf cnt4, toff, noff, part, bits, quad;
+  DevBuf mflag, moff;  // symmetric products: off-diagonal flags, mirror offsets
+  ScanWork mscan;
+  bool upper = false;  // the pass keeps only C nodes with I <= J
   int64_t cap_count = 0;
   Control* ctl_dev = nullptr;
   Control* ctl_host = nullptr;  // pinned
   void release(hipStream_t s);
   size_t held_bytes() const {
-    size_t b = cnt4.bytes + toff.bytes + noff.bytes + part.bytes + bits.bytes + quad.bytes;
+    size_t b = cnt4.bytes + toff.bytes + noff.bytes + part.bytes + bits.bytes + quad.bytes +
+               mflag.bytes + moff.bytes + mscan.part.bytes;
     for (int t = 0; t < kMaxTiers; ++t) b += nodes[t].bytes + nptr[t].bytes + ks[t].bytes;
     return b;
   }
@@ -243,11 +247,17 @@ Error run_cull(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double
 // The same in two halves: cull_launch queues the pass and the copy of the
 // control block to w.ctl_host; after the caller has synchronised `s`,
 // cull_finish regrows and resumes where needed and fills `out`.
+// With `upper` only the C blocks (i, j) with i <= j are kept (products
+// known to be symmetric: the other blocks are their mirrors).
 Error cull_launch(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
-                  bool want_pairs, hipStream_t s);
+                  bool want_pairs, hipStream_t s, bool upper = false);
 Error cull_finish(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
                   bool want_pairs, hipStream_t s, CullResult* out);
 Error ensure_control(CullWork& w);
+// Symmetric products: moff[x] = number of off-diagonal C blocks before C
+// block x of r's task list (their mirror slots follow the n_cblocks direct
+// ones), the total into *total_dev.
+Error launch_mirror_offsets(CullWork& w, const CullResult& r, int64_t* total_dev, hipStream_t s);
 // The 64-bit leaf masks of the tier d-2 frontier (see CullResult).  Each bit
 // repeats the decisions the tier walk took for that leaf product and its
 // tier d-1 parent.
@@ -298,7 +308,16 @@ struct GemmArgs {
   double* err_part;      // [nb * nb]
   // FP16 forms: set to 1 when a stored value leaves FP16's finite range.
   int32_t* overflow;
+  // Symmetric products (sym != 0): the task list holds only C blocks with
+  // i <= j; each off-diagonal block is also stored transposed as block
+  // (j, i) in slot n_nodes + moff[node], with the same norm and partials.
+  int sym;
+  const int64_t* moff;
 };
+// Slot of the mirror of C block `node` = (i, j), or -1.
+__device__ inline int64_t mirror_slot(const GemmArgs& g, int64_t node, int i, int j) {
+  return (g.sym && i != j) ? g.n_nodes + g.moff[node] : -1;
+}
 // Leaf-product kernels (all add the same products in the same order):
 //   block  one wave per C block;
 //   2x2    4 waves per 2 x 2 group of C blocks, operands staged in LDS;
@@ -407,6 +426,7 @@ struct RestArgs {
   double* trace_part;
   double* err_part;
   int64_t* counter;      // appended blocks
+  const int64_t* base_extra;  // symmetric products: mirror slots before the appended ones
 };
 void launch_sp2_rest(int prec, const RestArgs& r, hipStream_t s);
 void launch_sp2_rest_half(int prec, const RestArgs& r, hipStream_t s);

@@ -51,7 +51,9 @@ struct Epi {
     if (diag) tr += double(v);
     return v;
   }
-  __device__ inline void finish(const GemmArgs& g, int64_t node, int32_t ij, int lane) {
+  // ms: the mirror's slot (symmetric products), or -1.
+  __device__ inline void finish(const GemmArgs& g, int64_t node, int32_t ij, int lane,
+                                int64_t ms) {
     const int i = unpack_i(ij), j = unpack_j(ij);
     const double n2 = wave_sum(nrm);
     const double e2 = g.sp2 ? wave_sum(err) : 0.0;
@@ -64,6 +66,13 @@ struct Epi {
       if (g.sp2) {
         g.err_part[cell] = e2;
         if (i == j) g.trace_part[i] = t;
+      }
+      if (ms >= 0) {
+        const int64_t mcell = int64_t(j) * g.nb + i;
+        g.norm_c[mcell] = sqrt(n2);
+        g.map_c[mcell] = int32_t(ms);
+        g.coords_c[ms] = pack_ij(j, i);
+        if (g.sp2) g.err_part[mcell] = e2;
       }
     }
   }
@@ -173,6 +182,8 @@ __device__ __forceinline__ void f32_block(const GemmArgs& g, int64_t node, int l
     }
   }
   float* out = static_cast<float*>(g.pool_c) + node * kLeaf2;
+  const int64_t ms = uniform(mirror_slot(g, node, i, j));
+  float* outm = ms >= 0 ? static_cast<float*>(g.pool_c) + ms * kLeaf2 : nullptr;
   const float* xt = nullptr;
   if (g.sp2) {
     const int32_t sx = g.map_x[int64_t(i) * g.nb + j];
@@ -180,13 +191,19 @@ __device__ __forceinline__ void f32_block(const GemmArgs& g, int64_t node, int l
   }
   const int col = lane & 31, kk = lane >> 5;
   Epi<float> e;
+  v4f m4;
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = (r >> 2) * 8 + kk * 4 + (r & 3);
     const float x = xt ? xt[row * kLeaf + col] : 0.0f;
-    out[row * kLeaf + col] = e.apply(acc[r], x, g.sp2, g.square, i == j && row == col);
+    const float v = e.apply(acc[r], x, g.sp2, g.square, i == j && row == col);
+    out[row * kLeaf + col] = v;
+    // The mirror's row `col` holds this lane's 4 consecutive rows.
+    m4[r & 3] = v;
+    if ((r & 3) == 3 && outm)
+      *reinterpret_cast<v4f*>(outm + col * kLeaf + (r >> 2) * 8 + kk * 4) = m4;
   }
-  e.finish(g, node, ij, lane);
+  e.finish(g, node, ij, lane, ms);
 }
 
 __global__ void __launch_bounds__(256) k_leaf_gemm_f32(GemmArgs g) {
@@ -344,7 +361,7 @@ __global__ void __launch_bounds__(256) k_leaf_gemm_f32_2x2(GemmArgs g) {
     const float x = xt ? xt[row * kLeaf + col] : 0.0f;
     out[row * kLeaf + col] = e.apply(acc[r], x, g.sp2, g.square, i == j && row == col);
   }
-  e.finish(g, node, pack_ij(i, j), lane);
+  e.finish(g, node, pack_ij(i, j), lane, -1);
 }
 
 // ---- FP32 leaf products: one wave per 2 x 2 group, no barriers ---------------
@@ -481,19 +498,27 @@ __device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
     const int64_t node = uniform(g.sup_noff[4 * p + q]);
     const int i = 2 * I + (q >> 1), j = 2 * J + (q & 1);
     float* out = static_cast<float*>(g.pool_c) + node * kLeaf2;
+    const int64_t ms = uniform(mirror_slot(g, node, i, j));
+    float* outm = ms >= 0 ? static_cast<float*>(g.pool_c) + ms * kLeaf2 : nullptr;
     const float* xt = nullptr;
     if (g.sp2) {
       const int32_t sx = g.map_x[int64_t(i) * g.nb + j];
       if (sx >= 0) xt = static_cast<const float*>(g.pool_x) + int64_t(sx) * kLeaf2;
     }
     Epi<float> e;
+    v4f m4;
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int row = (r >> 2) * 8 + kk * 4 + (r & 3);
       const float x = xt ? xt[row * kLeaf + col] : 0.0f;
-      out[row * kLeaf + col] = e.apply(a[r], x, g.sp2, g.square, i == j && row == col);
+      const float v = e.apply(a[r], x, g.sp2, g.square, i == j && row == col);
+      out[row * kLeaf + col] = v;
+      // The mirror's row `col` holds this lane's 4 consecutive rows.
+      m4[r & 3] = v;
+      if ((r & 3) == 3 && outm)
+        *reinterpret_cast<v4f*>(outm + col * kLeaf + (r >> 2) * 8 + kk * 4) = m4;
     }
-    e.finish(g, node, pack_ij(i, j), lane);
+    e.finish(g, node, pack_ij(i, j), lane, ms);
   };
   emit(0, acc[0]);
   emit(1, acc[1]);
@@ -663,7 +688,7 @@ __global__ void __launch_bounds__(256) k_leaf_gemm_f32_4x4(GemmArgs g) {
       const float x = xt ? xt[rr * kLeaf + col] : 0.0f;
       out[rr * kLeaf + col] = e.apply(acc[r], x, g.sp2, g.square, i == j && rr == col);
     }
-    e.finish(g, node, pack_ij(i, j), lane);
+    e.finish(g, node, pack_ij(i, j), lane, -1);
   };
   emit(0, acc0);
   emit(1, acc1);
@@ -742,6 +767,8 @@ __device__ __forceinline__ void f64_block(const GemmArgs& g, int64_t node, int l
     }
   }
   double* out = static_cast<double*>(g.pool_c) + node * kLeaf2;
+  const int64_t ms = uniform(mirror_slot(g, node, i, j));
+  double* outm = ms >= 0 ? static_cast<double*>(g.pool_c) + ms * kLeaf2 : nullptr;
   const double* xt = nullptr;
   if (g.sp2) {
     const int32_t sx = g.map_x[int64_t(i) * g.nb + j];
@@ -757,9 +784,11 @@ __device__ __forceinline__ void f64_block(const GemmArgs& g, int64_t node, int l
       for (int r = 0; r < 4; ++r) {
         const int row = p * 16 + kk + 4 * r, col = q * 16 + m;
         const double x = xt ? xt[row * kLeaf + col] : 0.0;
-        out[row * kLeaf + col] = e.apply(acc[p][q][r], x, g.sp2, g.square, i == j && row == col);
+        const double v = e.apply(acc[p][q][r], x, g.sp2, g.square, i == j && row == col);
+        out[row * kLeaf + col] = v;
+        if (outm) outm[col * kLeaf + row] = v;
       }
-  e.finish(g, node, ij, lane);
+  e.finish(g, node, ij, lane, ms);
 }
 
 __global__ void __launch_bounds__(256) k_leaf_gemm_f64(GemmArgs g) {
@@ -800,7 +829,9 @@ __global__ void __launch_bounds__(256) k_sp2_rest(RestArgs r) {
   if (lane == 0) r.err_part[cell] = e;
   if (r.square) return;
   int64_t slot = 0;
-  if (lane == 0) slot = r.base_slot + atomicAdd(reinterpret_cast<unsigned long long*>(r.counter), 1ull);
+  if (lane == 0)
+    slot = r.base_slot + (r.base_extra ? *r.base_extra : 0) +
+           atomicAdd(reinterpret_cast<unsigned long long*>(r.counter), 1ull);
   slot = __shfl(slot, 0, 64);
   T* out = static_cast<T*>(r.pool_out) + slot * kLeaf2;
   double nrm = 0.0, tr = 0.0;

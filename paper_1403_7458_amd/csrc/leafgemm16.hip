@@ -87,12 +87,20 @@ struct HAcc<P, false> {
 
 // Epilogue: value c of C block (i, j) -> stored tile (hi, lo and their
 // transposes), SP2 update, FP64 norm, trace and ||C - X_n||^2 partials.
+constexpr int kSymPitch = kLeaf + 1;  // padded rows of the diagonal-block transpose
+
+// sym_lds: the wave's kLeaf * kSymPitch floats, used by the split forms for
+// diagonal blocks of symmetric products.
 template <int P>
 __device__ inline void epilogue(const GemmArgs& g, int64_t node, int i, int j, const HAcc<P>& acc,
-                                int lane) {
+                                int lane, float* sym_lds) {
   typedef typename Half<P>::T T;
   const int stride = (is_split(P) ? 4 : 2) * kLeaf2;
   T* out = static_cast<T*>(g.pool_c) + node * stride;
+  // Symmetric products: the mirror (j, i) is the transpose, i.e. the same
+  // parts with the row-major and transposed roles swapped.
+  const int64_t ms = uniform(mirror_slot(g, node, i, j));
+  T* outm = ms >= 0 ? static_cast<T*>(g.pool_c) + ms * stride : nullptr;
   const T* xt = nullptr;
   if (g.sp2) {
     const int32_t sx = g.map_x[int64_t(i) * g.nb + j];
@@ -101,10 +109,27 @@ __device__ inline void epilogue(const GemmArgs& g, int64_t node, int i, int j, c
   const int col = lane & 31, kk = lane >> 5;
   double nrm = 0.0, err = 0.0, tr = 0.0;
   bool over = false;
+  float cv[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) cv[r] = acc.value(r);
+  if (is_split(P) && g.sym && i == j) {
+    // A diagonal block of a symmetric product is symmetric, but the split
+    // forms add hi_a lo_b and lo_a hi_b in opposite orders for (a, b) and
+    // (b, a); the mean of the two is exactly symmetric.
+#pragma unroll
+    for (int r = 0; r < 16; ++r) sym_lds[((r >> 2) * 8 + kk * 4 + (r & 3)) * kSymPitch + col] = cv[r];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      cv[r] = 0.5f * (cv[r] + sym_lds[col * kSymPitch + (r >> 2) * 8 + kk * 4 + (r & 3)]);
+    __builtin_amdgcn_wave_barrier();
+  }
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int row = (r >> 2) * 8 + kk * 4 + (r & 3);
-    const float c = acc.value(r);
+    const float c = cv[r];
     float v = c;
     if (g.sp2) {
       const double x =
@@ -124,6 +149,14 @@ __device__ inline void epilogue(const GemmArgs& g, int64_t node, int i, int j, c
       out[half_part(2) + row * kLeaf + col] = lo;
       out[half_part(3) + col * kLeaf + row] = lo;
     }
+    if (outm) {
+      outm[col * kLeaf + row] = hi;
+      outm[half_part(1) + row * kLeaf + col] = hi;
+      if (is_split(P)) {
+        outm[half_part(2) + col * kLeaf + row] = lo;
+        outm[half_part(3) + row * kLeaf + col] = lo;
+      }
+    }
     const double stored = decode_half<P>(hi, lo);
     nrm += stored * stored;
     if (i == j && row == col) tr += stored;
@@ -141,6 +174,13 @@ __device__ inline void epilogue(const GemmArgs& g, int64_t node, int i, int j, c
       g.err_part[cell] = e2;
       if (i == j) g.trace_part[i] = t;
     }
+    if (ms >= 0) {
+      const int64_t mcell = int64_t(j) * g.nb + i;
+      g.norm_c[mcell] = sqrt(n2);
+      g.map_c[mcell] = int32_t(ms);
+      g.coords_c[ms] = pack_ij(j, i);
+      if (g.sp2) g.err_part[mcell] = e2;
+    }
     if (any_over && g.overflow) *g.overflow = 1;
   }
 }
@@ -149,7 +189,7 @@ __device__ inline void epilogue(const GemmArgs& g, int64_t node, int i, int j, c
 // registers, the next step's tiles in flight during the current products.
 template <int P>
 __device__ __forceinline__ void half_w2x2(const GemmArgs& g, int64_t p, int lane,
-                                          int32_t (*tab)[2 * kWBatch]) {
+                                          int32_t (*tab)[2 * kWBatch], float* sym_lds) {
   typedef typename Half<P>::T T;
   const int32_t IJ = uniform(g.sup_nodes[p]);
   const int I = unpack_i(IJ), J = unpack_j(IJ);
@@ -226,7 +266,8 @@ __device__ __forceinline__ void half_w2x2(const GemmArgs& g, int64_t p, int lane
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (uniform(g.sup_cnt4[4 * p + q]) <= 0) continue;
-    epilogue<P>(g, uniform(g.sup_noff[4 * p + q]), 2 * I + (q >> 1), 2 * J + (q & 1), acc[q], lane);
+    epilogue<P>(g, uniform(g.sup_noff[4 * p + q]), 2 * I + (q >> 1), 2 * J + (q & 1), acc[q], lane,
+                sym_lds);
   }
 }
 
@@ -234,25 +275,28 @@ __device__ __forceinline__ void half_w2x2(const GemmArgs& g, int64_t p, int lane
 template <int P, int kW>
 __global__ void __launch_bounds__(64 * kW) k_leaf_gemm_half_w2x2(GemmArgs g) {
   __shared__ int32_t s_tab[kW][5][2 * kWBatch];
+  __shared__ float s_sym[kW][is_split(P) ? kLeaf * kSymPitch : 1];
   const int wave = threadIdx.x >> 6;
   const int64_t p = uniform(xcd_contiguous_block() * kW + wave);
   if (p >= g.n_super) return;
-  half_w2x2<P>(g, p, threadIdx.x & 63, s_tab[wave]);
+  half_w2x2<P>(g, p, threadIdx.x & 63, s_tab[wave], s_sym[wave]);
 }
 
 template <int P, int kW>
 __global__ void __launch_bounds__(64 * kW) k_leaf_gemm_half_w2x2_batch(GemmBatch b) {
   __shared__ int32_t s_tab[kW][5][2 * kWBatch];
+  __shared__ float s_sym[kW][is_split(P) ? kLeaf * kSymPitch : 1];
   const int wave = threadIdx.x >> 6;
   int64_t p = 0;
   const GemmArgs* g = batch_locate(b, wave, p);
   if (!g) return;
-  half_w2x2<P>(*g, p, threadIdx.x & 63, s_tab[wave]);
+  half_w2x2<P>(*g, p, threadIdx.x & 63, s_tab[wave], s_sym[wave]);
 }
 
 // One wave per C block over the leaf task list (trees of one tier).
 template <int P>
-__device__ __forceinline__ void half_block(const GemmArgs& g, int64_t node, int lane) {
+__device__ __forceinline__ void half_block(const GemmArgs& g, int64_t node, int lane,
+                                           float* sym_lds) {
   typedef typename Half<P>::T T;
   const int32_t ij = uniform(g.nodes[node]);
   const int i = unpack_i(ij), j = unpack_j(ij);
@@ -270,22 +314,24 @@ __device__ __forceinline__ void half_block(const GemmArgs& g, int64_t node, int 
     load_frag<P>(pb + int64_t(sb) * stride, 1, lane, fb);
     acc.add(fa, fb);
   }
-  epilogue<P>(g, node, i, j, acc, lane);
+  epilogue<P>(g, node, i, j, acc, lane, sym_lds);
 }
 
 template <int P>
 __global__ void __launch_bounds__(256) k_leaf_gemm_half_block(GemmArgs g) {
+  __shared__ float s_sym[kWaves][is_split(P) ? kLeaf * kSymPitch : 1];
   const int64_t node = uniform(int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6));
   if (node >= g.n_nodes) return;
-  half_block<P>(g, node, threadIdx.x & 63);
+  half_block<P>(g, node, threadIdx.x & 63, s_sym[threadIdx.x >> 6]);
 }
 
 template <int P>
 __global__ void __launch_bounds__(256) k_leaf_gemm_half_block_batch(GemmBatch b) {
+  __shared__ float s_sym[kWaves][is_split(P) ? kLeaf * kSymPitch : 1];
   int64_t node = 0;
   const GemmArgs* g = batch_locate(b, threadIdx.x >> 6, node);
   if (!g) return;
-  half_block<P>(*g, node, threadIdx.x & 63);
+  half_block<P>(*g, node, threadIdx.x & 63, s_sym[threadIdx.x >> 6]);
 }
 
 // SP2 blocks of X_n with no executed product (see k_sp2_rest).
@@ -313,7 +359,8 @@ __global__ void __launch_bounds__(256) k_sp2_rest_half(RestArgs r) {
   if (r.square) return;
   int64_t slot = 0;
   if (lane == 0)
-    slot = r.base_slot + atomicAdd(reinterpret_cast<unsigned long long*>(r.counter), 1ull);
+    slot = r.base_slot + (r.base_extra ? *r.base_extra : 0) +
+           atomicAdd(reinterpret_cast<unsigned long long*>(r.counter), 1ull);
   slot = __shfl(slot, 0, 64);
   T* out = static_cast<T*>(r.pool_out) + slot * stride;
   double nrm = 0.0, tr = 0.0;

@@ -36,7 +36,7 @@ Error check_sp2(const double* f, int64_t n, int64_t ldf, int64_t n_occ, double t
   SPAMM_TRY(check_tau(tau));
   if (!valid_prec(opt.precision)) return err(SPAMM_ERR_INVALID_ARG, "unsupported precision");
   if (opt.max_iter < 1 || opt.max_iter > SP2_MAX_ITER || opt.min_iter < 0 ||
-      !(opt.tol >= 0.0) || !(opt.stall_floor >= 0.0))
+      !(opt.tol >= 0.0) || !(opt.stall_floor >= 0.0) || (opt.symmetric != 0 && opt.symmetric != 1))
     return err(SPAMM_ERR_INVALID_ARG, "bad sp2 options");
   return Error{};
 }
@@ -122,8 +122,16 @@ class Sp2Job {
     SPAMM_TRY(dev_alloc_n(&buf_.err_part, int64_t(x_->nb) * x_->nb, s_));
     st_.eps_min = sh_.eps_min;
     st_.eps_max = sh_.eps_max;
+    // Exactly symmetric F gives exactly symmetric X_0 (each entry is scaled
+    // on its own), and squares computed on the upper triangle and mirrored
+    // keep every X_n exactly symmetric.  The LDS-staged FP32 variants have
+    // no mirrored epilogue.
+    const int choice = leaf_kernel_choice();
+    sym_ = opt_.symmetric && sh_.max_asym == 0.0 &&
+           !(opt_.precision == SPAMM_FP32 && (choice == kLeaf2x2 || choice == kLeaf4x4));
+    st_.symmetric = sym_ ? 1 : 0;
     launch_sp2_reduce(x_->nb, buf_.trace_part, nullptr, nullptr, w_->ctl_dev, s_);
-    return cull_launch(*w_, x_, x_, tau_, false, s_);
+    return cull_launch(*w_, x_, x_, tau_, false, s_, sym_);
   }
   // After the synchronisation: the first task list and t_0.
   Error begun() {
@@ -135,9 +143,12 @@ class Sp2Job {
   Error front(GemmArgs* g, int64_t* products) {
     square_ = t_n_ > double(n_occ_);
     const int nb = x_->nb;
-    SPAMM_TRY(iterate(iter_[it_ & 1],
-                      std::max<int64_t>(cr_.n_cblocks + (square_ ? 0 : x_->n_blocks), 1), &y_));
     Control* ctl = w_->ctl_dev;
+    // Symmetric: the direct blocks, then at most as many mirrors.
+    const int64_t direct = (sym_ ? 2 : 1) * cr_.n_cblocks;
+    SPAMM_TRY(iterate(iter_[it_ & 1],
+                      std::max<int64_t>(direct + (square_ ? 0 : x_->n_blocks), 1), &y_));
+    if (sym_) SPAMM_TRY(launch_mirror_offsets(*w_, cr_, &ctl->scratch[3], s_));
     launch_sp2_prepare(y_->map, y_->norms + tier_offset(y_->depth), buf_.err_part, nb,
                        buf_.trace_part, &ctl->scratch[1], s_);
     *g = GemmArgs{};
@@ -153,7 +164,8 @@ class Sp2Job {
     g->sup_bits = cr_.sup_bits;
     g->sup_cnt4 = cr_.sup_cnt4;
     g->sup_noff = cr_.sup_noff;
-    if (opt_.precision == SPAMM_FP32 && cr_.n_quad > 0 && leaf_kernel_choice() == kLeaf4x4) {
+    if (!sym_ && opt_.precision == SPAMM_FP32 && cr_.n_quad > 0 &&
+        leaf_kernel_choice() == kLeaf4x4) {
       launch_quad_masks(cr_, x_, x_, tau_, s_);
       launch_scatter_nodes(cr_.nodes, cr_.n_cblocks, nb, y_->map, y_->coords, s_);
       g->n_quad = cr_.n_quad;
@@ -177,6 +189,8 @@ class Sp2Job {
     g->trace_part = buf_.trace_part;
     g->err_part = buf_.err_part;
     g->overflow = reinterpret_cast<int32_t*>(&ctl->scratch[2]);
+    g->sym = sym_ ? 1 : 0;
+    g->moff = sym_ ? static_cast<const int64_t*>(w_->moff.p) : nullptr;
     *products = cr_.n_tasks;
     return Error{};
   }
@@ -199,6 +213,7 @@ class Sp2Job {
       r.trace_part = buf_.trace_part;
       r.err_part = buf_.err_part;
       r.counter = &ctl->scratch[1];
+      r.base_extra = sym_ ? &ctl->scratch[3] : nullptr;
       launch_sp2_rest(opt_.precision, r, s_);
       launch_sp2_reduce(x_->nb, buf_.trace_part, buf_.err_part, nullptr, ctl, s_);
     }
@@ -214,7 +229,7 @@ class Sp2Job {
     // synchronisation of this iteration, which also brings back t_{n+1}
     // and e_n.
     culled_ = it + 1 < opt_.max_iter;
-    if (culled_) return cull_launch(*w_, y_, y_, tau_, false, s_);
+    if (culled_) return cull_launch(*w_, y_, y_, tau_, false, s_, sym_);
     SPAMM_HIP(hipMemcpyAsync(w_->ctl_host, ctl, sizeof(Control), hipMemcpyDeviceToHost, s_));
     return Error{};
   }
@@ -226,7 +241,7 @@ class Sp2Job {
       return err(SPAMM_ERR_NONFINITE, "SP2 iterate is not finite or leaves FP16's range");
     const double e_n = std::sqrt(h.sp2_err2);
     t_n_ = h.sp2_trace;
-    y_->n_blocks = y_direct_ + h.extra_blocks;
+    y_->n_blocks = y_direct_ + (sym_ ? h.scratch[3] : 0) + h.extra_blocks;
     errs_.push_back(e_n);
     st_.err[it_] = e_n;
     free_matrix(x_);
@@ -313,7 +328,7 @@ class Sp2Job {
   double t_n_ = 0.0, stall_at_ = 0.0;
   int it_ = 0;
   int stop_ = SP2_STOP_MAX_ITER;
-  bool done_ = false, square_ = false, culled_ = false;
+  bool done_ = false, square_ = false, culled_ = false, sym_ = false;
   int64_t total_exec_ = 0, y_direct_ = 0;
 };
 

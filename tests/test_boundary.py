@@ -46,8 +46,8 @@ def test_struct_sizes_match_the_header():
     # Sizes implied by the field lists of include/spamm.h (x86-64 System V).
     assert ctypes.sizeof(_lib.SpammInfo) == 48
     assert ctypes.sizeof(_lib.MultStats) == 48
-    assert ctypes.sizeof(_lib.Sp2Options) == 32
-    assert ctypes.sizeof(_lib.Sp2Stats) == 8 + 24 + 8 + 256 + 4 * 8 * 256
+    assert ctypes.sizeof(_lib.Sp2Options) == 40
+    assert ctypes.sizeof(_lib.Sp2Stats) == 16 + 24 + 8 + 256 + 4 * 8 * 256
     assert ctypes.sizeof(_lib.Profile) == 6 * 8 * 2 + 8
     assert ctypes.sizeof(_lib.ServerOptions) == 16
     assert ctypes.sizeof(_lib.ServerInfo) == 12 * 8
@@ -94,7 +94,7 @@ def test_sp2_options_defaults_come_from_the_library():
     o = _lib.Sp2Options()
     _lib.load().sp2_options_default(ctypes.byref(o))
     assert (o.precision, o.max_iter, o.min_iter, o.stall_rule) == (1, 100, 0, 1)
-    assert o.tol == 1e-8 and o.stall_floor == 0.0
+    assert o.tol == 1e-8 and o.stall_floor == 0.0 and o.symmetric == 1
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):

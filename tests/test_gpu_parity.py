@@ -260,14 +260,20 @@ def eigh_projector(f, n_occ):
     return v[:, :n_occ] @ v[:, :n_occ].T
 
 
+@pytest.mark.parametrize("symmetric", [True, False])
 @pytest.mark.parametrize("tau", [0.0, 1e-6])
-def test_sp2_fp64_matches_oracle(torch_dev, lib, tau):
+def test_sp2_fp64_matches_oracle(torch_dev, lib, tau, symmetric):
     w = water_cluster(8, 1.5, 2)
-    p, st = lib.sp2_solve(to_dev(torch_dev, w.f), w.n_occ, tau, precision="fp64")
+    p, st = lib.sp2_solve(to_dev(torch_dev, w.f), w.n_occ, tau, precision="fp64",
+                          symmetric=symmetric)
     r = sp2o.sp2(w.f, w.n_occ, tau)
     assert st["iterations"] == r.iterations
     assert st["branches"] == r.branches
-    assert st["n_exec"] == r.n_exec
+    assert st["symmetric"] == symmetric
+    # Symmetric squares execute the products of the C blocks with i <= j.
+    assert st["n_exec"] == (r.n_exec_upper if symmetric else r.n_exec)
+    if symmetric:
+        np.testing.assert_array_equal(p, p.T)
     np.testing.assert_allclose(st["traces"], r.traces, rtol=1e-12)
     np.testing.assert_allclose(st["errors"], r.errors, rtol=1e-6, atol=1e-12)
     assert rel(p, r.p) <= 1e-10
@@ -288,6 +294,30 @@ def test_sp2_fp32_matches_oracle(torch_dev, lib):
     assert rel(p, r.p) <= 1e-5
     assert abs(np.trace(p) - w.n_occ) <= 1e-4
     assert st["branches"][:20] == r.branches[:20]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "fp16x3", "bf16"])
+def test_sp2_symmetric_squares_match_full_squares(torch_dev, lib, prec):
+    """Upper-triangle squares with mirrored blocks against full squares: the
+    same iteration count and branches, about half the leaf products, P equal
+    to rounding (exactly symmetric), and the full form is used when F is not
+    exactly symmetric."""
+    w = water_cluster(16, 1.8, 4)
+    f = to_dev(torch_dev, w.f)
+    ps, ss = lib.sp2_solve(f, w.n_occ, 1e-6, precision=prec)
+    pf, sf = lib.sp2_solve(f, w.n_occ, 1e-6, precision=prec, symmetric=False)
+    assert ss["symmetric"] and not sf["symmetric"]
+    np.testing.assert_array_equal(ps, ps.T)
+    tol = {"fp64": 1e-12, "fp32": 1e-5, "fp16x3": 1e-5, "bf16": 1e-1}[prec]
+    assert rel(ps, pf) <= tol
+    if prec in ("fp64", "fp32"):
+        assert ss["branches"] == sf["branches"] and ss["iterations"] == sf["iterations"]
+        for a, b in zip(ss["n_exec"], sf["n_exec"]):
+            assert b / 2 <= a <= b / 2 + b / 8      # the diagonal blocks count once
+    g = w.f.copy()
+    g[3, 7] *= 1.0 + 2.0 ** -50                   # within the symmetry check, not exact
+    _, sg = lib.sp2_solve(to_dev(torch_dev, g), w.n_occ, 1e-6, precision=prec)
+    assert not sg["symmetric"]
 
 
 def test_sp2_c1_workload_fp64(torch_dev, lib):
@@ -429,17 +459,24 @@ def test_leaf_kernels_agree_bitwise(torch_dev, lib, prec, monkeypatch):
     f = to_dev(torch_dev, w.f)
     x0, _, _ = lib.sp2_initial_guess(f, prec)
     out = {}
+    sym = {}
     for kern in ("block", "2x2", "4x4", "w2x2", "w2x2s"):
         monkeypatch.setenv("SPAMM_LEAF_KERNEL", kern)
         c, st = lib.spamm_multiply(x0, x0, 1e-7)
-        p, s2 = lib.sp2_solve(f, w.n_occ, 1e-7, precision=prec, max_iter=6)
+        p, s2 = lib.sp2_solve(f, w.n_occ, 1e-7, precision=prec, max_iter=6, symmetric=False)
         out[kern] = (lib.spamm_to_dense(c), st["n_exec"], p, s2["errors"])
+        if kern in ("block", "w2x2", "w2x2s"):   # the kernels with a mirrored epilogue
+            sym[kern] = lib.sp2_solve(f, w.n_occ, 1e-7, precision=prec, max_iter=6)
     ref = out["block"]
     for kern in ("2x2", "4x4", "w2x2", "w2x2s"):
         np.testing.assert_array_equal(out[kern][0], ref[0])
         assert out[kern][1] == ref[1]
         np.testing.assert_array_equal(out[kern][2], ref[2])
         assert out[kern][3] == ref[3]
+    for kern in ("w2x2", "w2x2s"):
+        np.testing.assert_array_equal(sym[kern][0], sym["block"][0])
+        assert sym[kern][1]["errors"] == sym["block"][1]["errors"]
+        assert sym[kern][1]["symmetric"]
 
 
 # ---- 16-bit forms ----------------------------------------------------------------

@@ -212,3 +212,25 @@ def test_depth_zero_leaf_is_tested():
     c3, i3 = alg1.spamm_alg1(a, a, 3.99)
     assert i3["n_exec"] == 1
     np.testing.assert_allclose(c3[:4, :4], a @ a)
+
+
+def test_upper_count_is_the_restriction_of_the_executed_set(rng):
+    """n_exec_upper counts the executed (i, j, k) with i <= j (brute force);
+    for a symmetric matrix the task sets of (i, j) and (j, i) coincide, so
+    n_exec = 2 n_exec_upper - (executed products of diagonal blocks)."""
+    n = 200
+    a = rng.standard_normal((n, n)) * np.exp(-np.abs(np.subtract.outer(np.arange(n), np.arange(n))) / 30)
+    a = a + a.T
+    tau = 0.3
+    _, info = so.spamm(a, a, tau)
+    na = info["norms_a"]
+    nb = na.shape[0]
+    upper = diag = 0
+    for i in range(nb):
+        for j in range(nb):
+            for k in range(nb):
+                if na[i, k] * na[k, j] > tau:
+                    upper += i <= j
+                    diag += i == j
+    assert info["n_exec_upper"] == upper
+    assert info["n_exec"] == 2 * upper - diag
