@@ -635,6 +635,35 @@ CullWork::~CullWork() {
   if (ctl_host) (void)hipHostFree(ctl_host);
 }
 
+namespace {
+
+__global__ void k_offdiag_flags(const int32_t* __restrict__ nodes, const int64_t* len_dev,
+                                int64_t cap, int32_t* __restrict__ flag) {
+  int64_t n = *len_dev;
+  if (n < 0 || n > cap) n = 0;  // a pass that overflowed: recomputed after the regrowth
+  for (int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; x < n;
+       x += int64_t(gridDim.x) * blockDim.x)
+    flag[x] = unpack_i(nodes[x]) != unpack_j(nodes[x]) ? 1 : 0;
+}
+
+// Symmetric products: moff[x] = number of off-diagonal C blocks before leaf
+// node x (their mirrors take the slots after the direct ones), the total
+// into ctl->scratch[3].  Lengths come from the control block.
+Error mirror_offsets(CullWork& w, int d, hipStream_t s) {
+  const int64_t cap = std::max<int64_t>(w.cap_nodes[d], 1);
+  SPAMM_TRY(w.mflag.grow(size_t(cap) * sizeof(int32_t), s));
+  SPAMM_TRY(w.moff.grow(size_t(cap) * sizeof(int64_t), s));
+  Control* ctl = w.ctl_dev;
+  int32_t* flag = static_cast<int32_t*>(w.mflag.p);
+  const unsigned grid = unsigned(std::min<int64_t>((cap + 255) / 256, 1024));
+  k_offdiag_flags<<<grid, 256, 0, s>>>(static_cast<const int32_t*>(w.nodes[d].p),
+                                       &ctl->n_nodes[d], w.cap_nodes[d], flag);
+  return launch_scan(flag, static_cast<int64_t*>(w.moff.p), nullptr, nullptr, &ctl->n_nodes[d],
+                     w.cap_nodes[d], 1, 0, &ctl->scratch[3], nullptr, nullptr, w.mscan, s);
+}
+
+}  // namespace
+
 Error cull_launch(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
                   bool want_pairs, hipStream_t s, bool upper) {
   const int d = a->depth;
@@ -662,6 +691,7 @@ Error cull_launch(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, dou
     PhaseTimer timer(SPAMM_PHASE_CULL, s);
     launch_top(w, a, b, t_top, tau, want_pairs, s);
     for (int t = t_top; t < d; ++t) expand(w, a, b, t, tau, s);
+    if (upper) SPAMM_TRY(mirror_offsets(w, d, s));
     if (want_pairs)
       k_nonzero_pairs<<<1, 1024, 0, s>>>(a->norms + tier_offset(d), b->norms + tier_offset(d),
                                          a->nb, ctl);
@@ -703,10 +733,13 @@ Error cull_finish(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, dou
     ++out->restarts;
     PhaseTimer timer(SPAMM_PHASE_CULL, s);
     for (int t = bad - 1; t < d; ++t) expand(w, a, b, t, tau, s);
+    if (w.upper) SPAMM_TRY(mirror_offsets(w, d, s));
   }
   const Control& h = *w.ctl_host;
   out->n_cblocks = h.n_nodes[d];
   out->n_tasks = h.n_tasks[d];
+  out->n_mirrors = w.upper ? h.scratch[3] : 0;
+  out->moff = w.upper ? static_cast<const int64_t*>(w.moff.p) : nullptr;
   out->nonzero_pairs = want_pairs ? h.nonzero_pairs : -1;
   double e = 0.0;
   for (int t = 0; t <= d; ++t) e += h.err[t];
@@ -743,27 +776,6 @@ void launch_quad_masks(const CullResult& r, const spamm_matrix* a, const spamm_m
                                             b->norms + tier_offset(d - 1), a->norms + tier_offset(d),
                                             b->norms + tier_offset(d), d, tau, r.n_quad,
                                             r.quad_masks);
-}
-
-namespace {
-
-__global__ void k_offdiag_flags(const int32_t* __restrict__ nodes, int64_t n,
-                                int32_t* __restrict__ flag) {
-  const int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (x < n) flag[x] = unpack_i(nodes[x]) != unpack_j(nodes[x]) ? 1 : 0;
-}
-
-}  // namespace
-
-Error launch_mirror_offsets(CullWork& w, const CullResult& r, int64_t* total_dev, hipStream_t s) {
-  const int64_t n = std::max<int64_t>(r.n_cblocks, 1);
-  SPAMM_TRY(w.mflag.grow(size_t(n) * sizeof(int32_t), s));
-  SPAMM_TRY(w.moff.grow(size_t(n) * sizeof(int64_t), s));
-  int32_t* flag = static_cast<int32_t*>(w.mflag.p);
-  if (r.n_cblocks > 0)
-    k_offdiag_flags<<<unsigned((r.n_cblocks + 255) / 256), 256, 0, s>>>(r.nodes, r.n_cblocks, flag);
-  return launch_scan(flag, static_cast<int64_t*>(w.moff.p), nullptr, nullptr, nullptr, 0, 1,
-                     r.n_cblocks, total_dev, nullptr, nullptr, w.mscan, s);
 }
 
 void launch_scatter_nodes(const int32_t* nodes, int64_t n, int nb, int32_t* map_c,

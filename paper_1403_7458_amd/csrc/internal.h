@@ -211,6 +211,10 @@ struct CullWork {
 
 struct CullResult {
   int64_t n_cblocks = 0, n_tasks = 0, nonzero_pairs = 0;
+  // Passes with `upper`: the off-diagonal C blocks (their mirrors) and, per
+  // C block, the number of off-diagonal ones before it.
+  int64_t n_mirrors = 0;
+  const int64_t* moff = nullptr;
   double err_bound = 0.0;
   int restarts = 0;
   const int32_t* nodes = nullptr;
@@ -254,10 +258,7 @@ Error cull_launch(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, dou
 Error cull_finish(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
                   bool want_pairs, hipStream_t s, CullResult* out);
 Error ensure_control(CullWork& w);
-// Symmetric products: moff[x] = number of off-diagonal C blocks before C
-// block x of r's task list (their mirror slots follow the n_cblocks direct
-// ones), the total into *total_dev.
-Error launch_mirror_offsets(CullWork& w, const CullResult& r, int64_t* total_dev, hipStream_t s);
+
 // The 64-bit leaf masks of the tier d-2 frontier (see CullResult).  Each bit
 // repeats the decisions the tier walk took for that leaf product and its
 // tier d-1 parent.
@@ -426,7 +427,6 @@ struct RestArgs {
   double* trace_part;
   double* err_part;
   int64_t* counter;      // appended blocks
-  const int64_t* base_extra;  // symmetric products: mirror slots before the appended ones
 };
 void launch_sp2_rest(int prec, const RestArgs& r, hipStream_t s);
 void launch_sp2_rest_half(int prec, const RestArgs& r, hipStream_t s);

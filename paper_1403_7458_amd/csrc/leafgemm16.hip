@@ -359,8 +359,7 @@ __global__ void __launch_bounds__(256) k_sp2_rest_half(RestArgs r) {
   if (r.square) return;
   int64_t slot = 0;
   if (lane == 0)
-    slot = r.base_slot + (r.base_extra ? *r.base_extra : 0) +
-           atomicAdd(reinterpret_cast<unsigned long long*>(r.counter), 1ull);
+    slot = r.base_slot + atomicAdd(reinterpret_cast<unsigned long long*>(r.counter), 1ull);
   slot = __shfl(slot, 0, 64);
   T* out = static_cast<T*>(r.pool_out) + slot * stride;
   double nrm = 0.0, tr = 0.0;

@@ -144,13 +144,15 @@ class Sp2Job {
     square_ = t_n_ > double(n_occ_);
     const int nb = x_->nb;
     Control* ctl = w_->ctl_dev;
-    // Symmetric: the direct blocks, then at most as many mirrors.
-    const int64_t direct = (sym_ ? 2 : 1) * cr_.n_cblocks;
+    // The direct C blocks, their mirrors (symmetric squares), then the
+    // blocks of X_n carried over.
+    const int64_t direct = cr_.n_cblocks + cr_.n_mirrors;
     SPAMM_TRY(iterate(iter_[it_ & 1],
                       std::max<int64_t>(direct + (square_ ? 0 : x_->n_blocks), 1), &y_));
-    if (sym_) SPAMM_TRY(launch_mirror_offsets(*w_, cr_, &ctl->scratch[3], s_));
-    launch_sp2_prepare(y_->map, y_->norms + tier_offset(y_->depth), buf_.err_part, nb,
-                       buf_.trace_part, &ctl->scratch[1], s_);
+    if (!prepared_)
+      launch_sp2_prepare(y_->map, y_->norms + tier_offset(y_->depth), buf_.err_part, nb,
+                         buf_.trace_part, &ctl->scratch[1], s_);
+    prepared_ = false;
     *g = GemmArgs{};
     g->nb = nb;
     g->n_nodes = cr_.n_cblocks;
@@ -190,7 +192,7 @@ class Sp2Job {
     g->err_part = buf_.err_part;
     g->overflow = reinterpret_cast<int32_t*>(&ctl->scratch[2]);
     g->sym = sym_ ? 1 : 0;
-    g->moff = sym_ ? static_cast<const int64_t*>(w_->moff.p) : nullptr;
+    g->moff = cr_.moff;
     *products = cr_.n_tasks;
     return Error{};
   }
@@ -205,7 +207,7 @@ class Sp2Job {
       r.n_x = x_->n_blocks;
       r.pool_x = x_->pool;
       r.coords_x = x_->coords;
-      r.base_slot = cr_.n_cblocks;
+      r.base_slot = cr_.n_cblocks + cr_.n_mirrors;
       r.pool_out = y_->pool;
       r.map_out = y_->map;
       r.coords_out = y_->coords;
@@ -213,7 +215,6 @@ class Sp2Job {
       r.trace_part = buf_.trace_part;
       r.err_part = buf_.err_part;
       r.counter = &ctl->scratch[1];
-      r.base_extra = sym_ ? &ctl->scratch[3] : nullptr;
       launch_sp2_rest(opt_.precision, r, s_);
       launch_sp2_reduce(x_->nb, buf_.trace_part, buf_.err_part, nullptr, ctl, s_);
     }
@@ -224,13 +225,27 @@ class Sp2Job {
     st_.n_exec[it] = cr_.n_tasks;
     st_.n_blocks[it] = x_->n_blocks;
     total_exec_ += cr_.n_tasks;
-    y_direct_ = cr_.n_cblocks;
+    y_direct_ = cr_.n_cblocks + cr_.n_mirrors;
     // The next square's occlusion pass is queued before the one
     // synchronisation of this iteration, which also brings back t_{n+1}
     // and e_n.
     culled_ = it + 1 < opt_.max_iter;
-    if (culled_) return cull_launch(*w_, y_, y_, tau_, false, s_, sym_);
-    SPAMM_HIP(hipMemcpyAsync(w_->ctl_host, ctl, sizeof(Control), hipMemcpyDeviceToHost, s_));
+    if (!culled_) {
+      SPAMM_HIP(hipMemcpyAsync(w_->ctl_host, ctl, sizeof(Control), hipMemcpyDeviceToHost, s_));
+      return Error{};
+    }
+    SPAMM_TRY(cull_launch(*w_, y_, y_, tau_, false, s_, sym_));
+    // The next iterate's map, pyramid and partial sums are cleared now, so
+    // that after the synchronisation only the leaf products remain to be
+    // queued.  Its buffers are those of X_n, whose last reader (this
+    // iteration's rest of X_n) is already queued.
+    IterBuf& nb = iter_[(it + 1) & 1];
+    SPAMM_TRY(nb.map.grow(size_t(x_->nb) * x_->nb * sizeof(int32_t), s_));
+    SPAMM_TRY(nb.norms.grow(size_t(norms_size(x_->depth)) * sizeof(double), s_));
+    launch_sp2_prepare(static_cast<int32_t*>(nb.map.p),
+                       static_cast<double*>(nb.norms.p) + tier_offset(x_->depth), buf_.err_part,
+                       x_->nb, buf_.trace_part, &ctl->scratch[1], s_);
+    prepared_ = true;
     return Error{};
   }
 
@@ -241,7 +256,7 @@ class Sp2Job {
       return err(SPAMM_ERR_NONFINITE, "SP2 iterate is not finite or leaves FP16's range");
     const double e_n = std::sqrt(h.sp2_err2);
     t_n_ = h.sp2_trace;
-    y_->n_blocks = y_direct_ + (sym_ ? h.scratch[3] : 0) + h.extra_blocks;
+    y_->n_blocks = y_direct_ + h.extra_blocks;
     errs_.push_back(e_n);
     st_.err[it_] = e_n;
     free_matrix(x_);
@@ -328,7 +343,7 @@ class Sp2Job {
   double t_n_ = 0.0, stall_at_ = 0.0;
   int it_ = 0;
   int stop_ = SP2_STOP_MAX_ITER;
-  bool done_ = false, square_ = false, culled_ = false, sym_ = false;
+  bool done_ = false, square_ = false, culled_ = false, sym_ = false, prepared_ = false;
   int64_t total_exec_ = 0, y_direct_ = 0;
 };
 
