@@ -212,6 +212,9 @@ def main():
     ap.add_argument("--decay", type=float, default=1.5)
     ap.add_argument("--precision", default="fp32",
                     choices=["fp64", "fp32", "bf16", "fp16", "bf16x3", "fp16x3"])
+    ap.add_argument("--full-square-reference", action="store_true",
+                    help="also run one untimed solve with full squares and report the "
+                         "full-square-equivalent rate")
     ap.add_argument("--compare-fp64", action="store_true",
                     help="also solve with FP64 leaves and report the error against it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -271,10 +274,11 @@ def main():
     tr_err = abs(float(torch.trace(pt)) - n_occ)
     idem = float(torch.linalg.norm(pt @ pt - pt))
 
-    # The same solve with full squares (untimed): the leaf products the
-    # plain method executes, for the full-square-equivalent rate.
-    full_products = execs
-    if stats.get("symmetric"):
+    # With --full-square-reference, the same solve with full squares
+    # (untimed): the leaf products the plain method executes, for the
+    # full-square-equivalent rate.
+    full_products = None
+    if args.full_square_reference and stats.get("symmetric"):
         _, sfull = sp.sp2_solve(f, n_occ, tau, out=torch.empty_like(f), precision=prec,
                                 stream=stream, symmetric=False)
         full_products = sfull["n_exec_total"]
@@ -309,6 +313,20 @@ def main():
                 "launches": launches, "mean_launch_ms": round(gemm_ms, 4),
                 "products_per_launch": round(per_launch, 1)}
     phase_ms = {k: round(v / args.steps, 3) for k, v in prof["ms"].items()}
+    # HBM-bound passes: algorithmic bytes over the phase time per solve.
+    # Ingest: one read of F and one write of X_0's tiles; output: one read of
+    # P's tiles and one write of the dense FP64 P.
+    tile = {"fp64": 8192, "fp32": 4096, "bf16": 4096, "fp16": 4096}.get(prec, 8192)
+    tiles0 = stats["n_blocks"][0] * tile
+    tiles_p = stats["n_blocks"][-1] * tile
+    passes = {}
+    for name, phase, nbytes in (("ingest", "tree", 8 * n * n + tiles0),
+                                ("output", "dense", 8 * n * n + tiles_p)):
+        ms = prof["ms"][phase] / args.steps
+        if ms > 0:
+            gbs = nbytes / (ms * 1e-3) / 1e9
+            passes[name] = {"bytes": nbytes, "ms": round(ms, 4), "gbs": round(gbs, 1),
+                            "frac_of_hbm_peak": round(gbs / PEAK_HBM_GBS, 4)}
 
     multiply = {}
     x0 = None
@@ -379,10 +397,11 @@ def main():
         "sp2": {"iterations": stats["iterations"], "stop": stats["stop"],
                 "symmetric_squares": bool(stats.get("symmetric")),
                 "leaf_products": execs, "leaf_products_full_squares": full_products,
-                "full_square_equivalent_gflops": round(
+                "full_square_equivalent_gflops": None if full_products is None else round(
                     LEAF_FLOP * full_products * args.steps / elapsed / 1e9, 1),
                 "trace_error": tr_err, "idempotency": idem, "accuracy": accuracy},
         "phase_ms_per_step": phase_ms,
+        "hbm_passes": passes,
         "multiply": multiply,
         "serving": serve,
         "roofline": roofline,

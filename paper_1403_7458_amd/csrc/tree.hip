@@ -57,7 +57,10 @@ __global__ void __launch_bounds__(256) k_leaf_norms_dense(const double* __restri
   if (bad) scale->nonfinite = 1;
   if (lane == 0) {
     leaf[blk] = sqrt(s);
-    if (mx > 0.0)
+    // One address for every block: skip the atomic when the running maximum
+    // (which only grows) already covers this block, so that the blocks do
+    // not queue up behind each other on it.
+    if (mx > 0.0 && mx > *reinterpret_cast<volatile const double*>(&scale->max_val))
       atomicMax(reinterpret_cast<unsigned long long*>(&scale->max_val),
                 static_cast<unsigned long long>(__double_as_longlong(mx)));
   }
