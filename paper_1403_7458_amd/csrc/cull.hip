@@ -646,6 +646,37 @@ __global__ void k_offdiag_flags(const int32_t* __restrict__ nodes, const int64_t
     flag[x] = unpack_i(nodes[x]) != unpack_j(nodes[x]) ? 1 : 0;
 }
 
+// The same for short lists, in one workgroup: each thread counts a
+// contiguous chunk, one scan over the 1024 chunk counts, then offsets.
+constexpr int64_t kMirrorSmall = 65536;
+__global__ void __launch_bounds__(1024) k_mirror_small(const int32_t* __restrict__ nodes,
+                                                       const int64_t* len_dev, int64_t cap,
+                                                       int64_t* __restrict__ moff,
+                                                       int64_t* total) {
+  __shared__ int64_t s[1024];
+  int64_t n = *len_dev;
+  if (n < 0 || n > cap) n = 0;
+  const int t = threadIdx.x;
+  const int64_t chunk = (n + 1023) / 1024;
+  const int64_t b0 = min(n, t * chunk), b1 = min(n, b0 + chunk);
+  int64_t c = 0;
+  for (int64_t x = b0; x < b1; ++x) c += unpack_i(nodes[x]) != unpack_j(nodes[x]);
+  s[t] = c;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t add = t >= off ? s[t - off] : 0;
+    __syncthreads();
+    s[t] += add;
+    __syncthreads();
+  }
+  int64_t run = s[t] - c;
+  for (int64_t x = b0; x < b1; ++x) {
+    moff[x] = run;
+    run += unpack_i(nodes[x]) != unpack_j(nodes[x]);
+  }
+  if (t == 1023) *total = s[1023];
+}
+
 // Symmetric products: moff[x] = number of off-diagonal C blocks before leaf
 // node x (their mirrors take the slots after the direct ones), the total
 // into ctl->scratch[3].  Lengths come from the control block.
@@ -654,6 +685,12 @@ Error mirror_offsets(CullWork& w, int d, hipStream_t s) {
   SPAMM_TRY(w.mflag.grow(size_t(cap) * sizeof(int32_t), s));
   SPAMM_TRY(w.moff.grow(size_t(cap) * sizeof(int64_t), s));
   Control* ctl = w.ctl_dev;
+  if (w.cap_nodes[d] <= kMirrorSmall) {
+    k_mirror_small<<<1, 1024, 0, s>>>(static_cast<const int32_t*>(w.nodes[d].p), &ctl->n_nodes[d],
+                                      w.cap_nodes[d], static_cast<int64_t*>(w.moff.p),
+                                      &ctl->scratch[3]);
+    return Error{};
+  }
   int32_t* flag = static_cast<int32_t*>(w.mflag.p);
   const unsigned grid = unsigned(std::min<int64_t>((cap + 255) / 256, 1024));
   k_offdiag_flags<<<grid, 256, 0, s>>>(static_cast<const int32_t*>(w.nodes[d].p),

@@ -195,7 +195,8 @@ __global__ void k_pyramid_level(double* __restrict__ norms, int t) {
   norms[tier_offset(t) + x] = parent_norm(ch, 2 * w, x / w, x % w);
 }
 
-// Tiers t_top .. 0 in one workgroup (4^t_top <= blockDim).
+// Tiers t_top .. 0 in one workgroup (each tier reads the one below, written
+// by this workgroup before the barrier).
 __global__ void __launch_bounds__(1024) k_pyramid_top(double* __restrict__ norms, int t_top) {
   for (int t = t_top; t >= 0; --t) {
     const int64_t w = int64_t(1) << t;
@@ -439,8 +440,10 @@ void launch_write_tiles(const double* a, int64_t lda, const spamm_matrix* m, con
 
 void launch_pyramid(const spamm_matrix* m, hipStream_t s) {
   PhaseTimer timer(SPAMM_PHASE_PYRAMID, s);
+  // Tiers of up to 4^6 nodes go to the single-workgroup kernel (4 nodes per
+  // thread): one launch instead of one per tier for trees of depth <= 7.
   int t = m->depth - 1;
-  for (; t > 4; --t) {
+  for (; t > 6; --t) {
     const int64_t w2 = int64_t(1) << (2 * t);
     k_pyramid_level<<<grid_for(w2, 256), 256, 0, s>>>(m->norms, t);
   }
