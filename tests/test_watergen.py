@@ -59,3 +59,28 @@ def test_request_stream():
     assert np.all(np.diff(arr) >= 0)
     assert 8.0 < arr[-1] < 20.0      # mean gap 50 ms
     assert [q.seed for q in r] == [q.seed for q in request_stream(256, 20.0, seed=0)]
+
+
+def test_device_generator_follows_the_same_recipe():
+    """The torch generator (run here on the CPU device) builds the same kind
+    of matrix: exactly symmetric, diagonal -1 / +1 by orbital, the same
+    centres, and off-diagonal magnitudes following 0.3 exp(-d / decay)."""
+    import torch
+    from watergen import water_cluster_torch
+    f, n_occ = water_cluster_torch(12, 1.7, 5, device="cpu")
+    w = water_cluster(12, 1.7, 5)
+    f = f.numpy()
+    assert f.shape == w.f.shape and n_occ == w.n_occ
+    assert np.array_equal(f, f.T)
+    assert np.array_equal(np.diag(f), np.diag(w.f))
+    # Per molecule pair, the RMS of the 25 x 25 block is 0.3 exp(-d / decay)
+    # up to sampling noise (625 normals); the same holds for numpy's draws.
+    d = np.linalg.norm(w.centres[:, None] - w.centres[None], axis=2)
+    env = 0.3 * np.exp(-d / 1.7)
+    blocks = f.reshape(12, 25, 12, 25).transpose(0, 2, 1, 3)
+    off = ~np.eye(12, dtype=bool)
+    rms = np.sqrt((blocks ** 2).mean(axis=(2, 3)))[off]
+    assert np.allclose(rms / env[off], 1.0, atol=0.2)
+    # Deterministic per seed.
+    g, _ = water_cluster_torch(12, 1.7, 5, device="cpu")
+    assert np.array_equal(g.numpy(), f)
