@@ -207,6 +207,9 @@ void spamm_tasks_destroy(spamm_tasks* t); /* NULL-safe */
  * e_n = ||C - X_n||_F, X_{n+1} = C if t_n > n_occ else 2 X_n - C, stopping
  * on e_n < tol, on a stall (stall_rule) or at max_iter.  P = X_{n+1} of the
  * stopping iteration.  Traces, e_n, the branch and the stop test are FP64.
+ * With an exactly symmetric F (and opt->symmetric) each square computes the
+ * C blocks (i, j) with i <= j and mirrors the rest (see sp2_options).
+ * Device work runs on `stream`; the call returns after P is written.
  *
  * f:      n x n FP64 symmetric, row-major, ldf >= n; host or device.
  * n_occ:  0 <= n_occ <= n.

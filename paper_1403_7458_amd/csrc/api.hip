@@ -1,5 +1,6 @@
 // C ABI of libspamm: argument checks, handle management, device memory,
-// kernel timing and the host side of SpAMM (Eq. 4) and SP2 (Sec. 4).
+// kernel timing and the host side of SpAMM (Eq. 4).  SP2 and the serving
+// form are in sp2.hip.
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
