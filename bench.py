@@ -212,6 +212,8 @@ def main():
     ap.add_argument("--decay", type=float, default=1.5)
     ap.add_argument("--precision", default="fp32",
                     choices=["fp64", "fp32", "bf16", "fp16", "bf16x3", "fp16x3"])
+    ap.add_argument("--full-squares", action="store_true",
+                    help="SP2 without symmetric squares (every C block computed)")
     ap.add_argument("--full-square-reference", action="store_true",
                     help="also run one untimed solve with full squares and report the "
                          "full-square-equivalent rate")
@@ -248,7 +250,8 @@ def main():
     p = torch.empty_like(f)
 
     def solve():
-        return sp.sp2_solve(f, n_occ, tau, out=p, precision=prec, stream=stream)
+        return sp.sp2_solve(f, n_occ, tau, out=p, precision=prec, stream=stream,
+                            symmetric=not args.full_squares)
 
     for _ in range(args.warmup):
         solve()
