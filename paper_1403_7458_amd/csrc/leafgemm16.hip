@@ -186,8 +186,10 @@ __device__ inline void epilogue(const GemmArgs& g, int64_t node, int i, int j, c
 }
 
 // One wave per 2 x 2 group of C blocks (tier d-1 node), operands in
-// registers, the next step's tiles in flight during the current products.
-template <int P>
+// registers; kAhead = 2: the next step's tiles in flight during the current
+// products; 1: one operand set (fewer registers, other waves hide the
+// latency).
+template <int P, int kAhead>
 __device__ __forceinline__ void half_w2x2(const GemmArgs& g, int64_t p, int lane,
                                           int32_t (*tab)[2 * kWBatch], float* sym_lds) {
   typedef typename Half<P>::T T;
@@ -239,7 +241,12 @@ __device__ __forceinline__ void half_w2x2(const GemmArgs& g, int64_t p, int lane
       if (m & 4) acc[2].add(ra[1], rb[0]);
       if (m & 8) acc[3].add(ra[1], rb[1]);
     };
-    if (n_steps > 0) {
+    if (kAhead == 1) {
+      for (int x = 0; x < n_steps; ++x) {
+        fetch(x, fa[0], fb[0]);
+        compute(x, fa[0], fb[0]);
+      }
+    } else if (n_steps > 0) {
       fetch(0, fa[0], fb[0]);
       int x = 0;
       for (; x + 2 < n_steps; x += 2) {
@@ -272,17 +279,17 @@ __device__ __forceinline__ void half_w2x2(const GemmArgs& g, int64_t p, int lane
 }
 
 // kW: waves (2 x 2 groups) per workgroup.
-template <int P, int kW>
+template <int P, int kW, int kAhead>
 __global__ void __launch_bounds__(64 * kW) k_leaf_gemm_half_w2x2(GemmArgs g) {
   __shared__ int32_t s_tab[kW][5][2 * kWBatch];
   __shared__ float s_sym[kW][is_split(P) ? kLeaf * kSymPitch : 1];
   const int wave = threadIdx.x >> 6;
   const int64_t p = uniform(xcd_contiguous_block() * kW + wave);
   if (p >= g.n_super) return;
-  half_w2x2<P>(g, p, threadIdx.x & 63, s_tab[wave], s_sym[wave]);
+  half_w2x2<P, kAhead>(g, p, threadIdx.x & 63, s_tab[wave], s_sym[wave]);
 }
 
-template <int P, int kW>
+template <int P, int kW, int kAhead>
 __global__ void __launch_bounds__(64 * kW) k_leaf_gemm_half_w2x2_batch(GemmBatch b) {
   __shared__ int32_t s_tab[kW][5][2 * kWBatch];
   __shared__ float s_sym[kW][is_split(P) ? kLeaf * kSymPitch : 1];
@@ -290,7 +297,7 @@ __global__ void __launch_bounds__(64 * kW) k_leaf_gemm_half_w2x2_batch(GemmBatch
   int64_t p = 0;
   const GemmArgs* g = batch_locate(b, wave, p);
   if (!g) return;
-  half_w2x2<P>(*g, p, threadIdx.x & 63, s_tab[wave], s_sym[wave]);
+  half_w2x2<P, kAhead>(*g, p, threadIdx.x & 63, s_tab[wave], s_sym[wave]);
 }
 
 // One wave per C block over the leaf task list (trees of one tier).
@@ -386,16 +393,36 @@ __global__ void __launch_bounds__(256) k_sp2_rest_half(RestArgs r) {
   }
 }
 
-template <int P>
-void launch_p(const GemmArgs& g, hipStream_t s) {
+// Operand sets in flight per wave of the 16-bit 2 x 2 kernels
+// (SPAMM_HALF_AHEAD = 1 or 2 overrides).  Measured: one set lets the plain
+// forms run two waves per SIMD (BF16, 150 molecules: +27%); the split forms
+// stay at one wave per SIMD either way and keep the look-ahead (1000
+// molecules: +3%).
+int half_ahead(int prec) {
+  const char* v = std::getenv("SPAMM_HALF_AHEAD");
+  if (v && std::strcmp(v, "1") == 0) return 1;
+  if (v && std::strcmp(v, "2") == 0) return 2;
+  return is_split(prec) ? 2 : 1;
+}
+
+template <int P, int kA>
+void launch_w2x2_p(const GemmArgs& g, hipStream_t s) {
   const int w = w2x2_waves(g.n_super);
   const unsigned gw = unsigned((g.n_super + w - 1) / w);
-  if (g.n_super > 0 && w == 1)
-    k_leaf_gemm_half_w2x2<P, 1><<<gw, 64, 0, s>>>(g);
-  else if (g.n_super > 0 && w == 2)
-    k_leaf_gemm_half_w2x2<P, 2><<<gw, 128, 0, s>>>(g);
+  if (w == 1)
+    k_leaf_gemm_half_w2x2<P, 1, kA><<<gw, 64, 0, s>>>(g);
+  else if (w == 2)
+    k_leaf_gemm_half_w2x2<P, 2, kA><<<gw, 128, 0, s>>>(g);
+  else
+    k_leaf_gemm_half_w2x2<P, 4, kA><<<gw, 256, 0, s>>>(g);
+}
+
+template <int P>
+void launch_p(const GemmArgs& g, hipStream_t s) {
+  if (g.n_super > 0 && half_ahead(P) == 1)
+    launch_w2x2_p<P, 1>(g, s);
   else if (g.n_super > 0)
-    k_leaf_gemm_half_w2x2<P, 4><<<gw, 256, 0, s>>>(g);
+    launch_w2x2_p<P, 2>(g, s);
   else
     k_leaf_gemm_half_block<P><<<unsigned((g.n_nodes + kWaves - 1) / kWaves), 256, 0, s>>>(g);
 }
@@ -408,12 +435,19 @@ void launch_batch_p(const GemmArgs* host, const GemmArgs* dev, int n, hipStream_
   const int w = w2x2_waves(groups);
   for_each_batch(dev, n, w, [&](int r) { return host[r].n_nodes > 0 ? host[r].n_super : 0; },
                  [&](const GemmBatch& b) {
-                   if (w == 1)
-                     k_leaf_gemm_half_w2x2_batch<P, 1><<<grid(b), 64, 0, s>>>(b);
+                   const bool a1 = half_ahead(P) == 1;
+                   if (w == 1 && a1)
+                     k_leaf_gemm_half_w2x2_batch<P, 1, 1><<<grid(b), 64, 0, s>>>(b);
+                   else if (w == 1)
+                     k_leaf_gemm_half_w2x2_batch<P, 1, 2><<<grid(b), 64, 0, s>>>(b);
+                   else if (w == 2 && a1)
+                     k_leaf_gemm_half_w2x2_batch<P, 2, 1><<<grid(b), 128, 0, s>>>(b);
                    else if (w == 2)
-                     k_leaf_gemm_half_w2x2_batch<P, 2><<<grid(b), 128, 0, s>>>(b);
+                     k_leaf_gemm_half_w2x2_batch<P, 2, 2><<<grid(b), 128, 0, s>>>(b);
+                   else if (a1)
+                     k_leaf_gemm_half_w2x2_batch<P, 4, 1><<<grid(b), 256, 0, s>>>(b);
                    else
-                     k_leaf_gemm_half_w2x2_batch<P, 4><<<grid(b), 256, 0, s>>>(b);
+                     k_leaf_gemm_half_w2x2_batch<P, 4, 2><<<grid(b), 256, 0, s>>>(b);
                  });
   for_each_batch(dev, n, kWaves, [&](int r) { return host[r].n_super > 0 ? 0 : host[r].n_nodes; },
                  [&](const GemmBatch& b) { k_leaf_gemm_half_block_batch<P><<<grid(b), 256, 0, s>>>(b); });
