@@ -81,6 +81,22 @@ __device__ inline double decode_half(typename Half<P>::T hi, typename Half<P>::T
   return v;
 }
 
+// The same in FP32, exact for values that FP32 holds: hi + lo * 2^-L spans
+// at most 22 significant bits, and v - hi is exact for hi = round16(v).
+template <int P>
+__device__ inline void encode_half_f(float v, typename Half<P>::T& hi, typename Half<P>::T& lo) {
+  typedef typename Half<P>::T T;
+  hi = T(v);
+  lo = is_split(P) ? T((v - float(hi)) * lo_scale(P)) : T(0.0f);
+}
+
+template <int P>
+__device__ inline float decode_half_f(typename Half<P>::T hi, typename Half<P>::T lo) {
+  float v = float(hi);
+  if (is_split(P)) v += float(lo) * (1.0f / lo_scale(P));
+  return v;
+}
+
 // Element offsets of the parts of a 16-bit tile.
 __host__ __device__ constexpr int64_t half_part(int part) { return int64_t(part) * kLeaf2; }
 

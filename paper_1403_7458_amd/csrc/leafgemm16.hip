@@ -92,7 +92,7 @@ constexpr int kSymPitch = kLeaf + 1;  // padded rows of the diagonal-block trans
 // sym_lds: the wave's kLeaf * kSymPitch floats, used by the split forms for
 // diagonal blocks of symmetric products.
 template <int P>
-__device__ inline void epilogue(const GemmArgs& g, int64_t node, int i, int j, const HAcc<P>& acc,
+__device__ __forceinline__ void epilogue(const GemmArgs& g, int64_t node, int i, int j, const HAcc<P>& acc,
                                 int lane, float* sym_lds) {
   typedef typename Half<P>::T T;
   const int stride = (is_split(P) ? 4 : 2) * kLeaf2;
@@ -132,17 +132,17 @@ __device__ inline void epilogue(const GemmArgs& g, int64_t node, int i, int j, c
     const float c = cv[r];
     float v = c;
     if (g.sp2) {
-      const double x =
-          xt ? decode_half<P>(xt[row * kLeaf + col],
-                              is_split(P) ? xt[half_part(2) + row * kLeaf + col] : T(0.0f))
-             : 0.0;
-      v = g.square ? c : float(2.0 * x - double(c));
-      const double d = double(c) - x;
+      const float x =
+          xt ? decode_half_f<P>(xt[row * kLeaf + col],
+                                is_split(P) ? xt[half_part(2) + row * kLeaf + col] : T(0.0f))
+             : 0.0f;
+      v = g.square ? c : 2.0f * x - c;
+      const double d = double(c) - double(x);
       err += d * d;
     }
     over |= !(fabsf(v) <= float(half_max(P)));
     T hi, lo;
-    encode_half<P>(double(v), hi, lo);
+    encode_half_f<P>(v, hi, lo);
     out[row * kLeaf + col] = hi;
     out[half_part(1) + col * kLeaf + row] = hi;
     if (is_split(P)) {
@@ -157,7 +157,7 @@ __device__ inline void epilogue(const GemmArgs& g, int64_t node, int i, int j, c
         outm[half_part(3) + row * kLeaf + col] = lo;
       }
     }
-    const double stored = decode_half<P>(hi, lo);
+    const double stored = double(decode_half_f<P>(hi, lo));
     nrm += stored * stored;
     if (i == j && row == col) tr += stored;
   }
@@ -279,8 +279,10 @@ __device__ __forceinline__ void half_w2x2(const GemmArgs& g, int64_t p, int lane
 }
 
 // kW: waves (2 x 2 groups) per workgroup.
+// With one operand set the kernels are held to two waves per SIMD (the
+// split forms then keep their accumulators in VGPRs and still fit).
 template <int P, int kW, int kAhead>
-__global__ void __launch_bounds__(64 * kW) k_leaf_gemm_half_w2x2(GemmArgs g) {
+__global__ void __launch_bounds__(64 * kW, kAhead == 1 ? 2 : 1) k_leaf_gemm_half_w2x2(GemmArgs g) {
   __shared__ int32_t s_tab[kW][5][2 * kWBatch];
   __shared__ float s_sym[kW][is_split(P) ? kLeaf * kSymPitch : 1];
   const int wave = threadIdx.x >> 6;
@@ -290,7 +292,8 @@ __global__ void __launch_bounds__(64 * kW) k_leaf_gemm_half_w2x2(GemmArgs g) {
 }
 
 template <int P, int kW, int kAhead>
-__global__ void __launch_bounds__(64 * kW) k_leaf_gemm_half_w2x2_batch(GemmBatch b) {
+__global__ void __launch_bounds__(64 * kW, kAhead == 1 ? 2 : 1)
+    k_leaf_gemm_half_w2x2_batch(GemmBatch b) {
   __shared__ int32_t s_tab[kW][5][2 * kWBatch];
   __shared__ float s_sym[kW][is_split(P) ? kLeaf * kSymPitch : 1];
   const int wave = threadIdx.x >> 6;
@@ -393,16 +396,22 @@ __global__ void __launch_bounds__(256) k_sp2_rest_half(RestArgs r) {
   }
 }
 
-// Operand sets in flight per wave of the 16-bit 2 x 2 kernels
-// (SPAMM_HALF_AHEAD = 1 or 2 overrides).  Measured: one set lets the plain
-// forms run two waves per SIMD (BF16, 150 molecules: +27%); the split forms
-// stay at one wave per SIMD either way and keep the look-ahead (1000
-// molecules: +3%).
-int half_ahead(int prec) {
+// Operand sets in flight per wave of the 16-bit 2 x 2 kernels for a launch
+// of `groups` groups (SPAMM_HALF_AHEAD = 1 or 2 overrides).  One set holds
+// the kernels to fewer registers: the plain forms run three waves per SIMD
+// and the split forms two instead of one.  Measured: the extra waves win
+// while a single product is a few thousand groups (150 molecules, 3,481
+// groups: BF16 +13%, split FP16 +3%); with 10^5 groups (1000 molecules) the
+// look-ahead hides more of the operand fetch than the extra waves do (BF16
+// +5%, split FP16 +18%), and so it does in the batched launches of a serving
+// stream of mixed sizes (split FP16 +11% over one set, +7% over choosing by
+// the batch's group count).
+int half_ahead(int prec, int64_t groups, bool batched) {
   const char* v = std::getenv("SPAMM_HALF_AHEAD");
   if (v && std::strcmp(v, "1") == 0) return 1;
   if (v && std::strcmp(v, "2") == 0) return 2;
-  return is_split(prec) ? 2 : 1;
+  if (batched && is_split(prec)) return 2;
+  return groups >= kManyGroups ? 2 : 1;
 }
 
 template <int P, int kA>
@@ -419,7 +428,7 @@ void launch_w2x2_p(const GemmArgs& g, hipStream_t s) {
 
 template <int P>
 void launch_p(const GemmArgs& g, hipStream_t s) {
-  if (g.n_super > 0 && half_ahead(P) == 1)
+  if (g.n_super > 0 && half_ahead(P, g.n_super, false) == 1)
     launch_w2x2_p<P, 1>(g, s);
   else if (g.n_super > 0)
     launch_w2x2_p<P, 2>(g, s);
@@ -435,7 +444,7 @@ void launch_batch_p(const GemmArgs* host, const GemmArgs* dev, int n, hipStream_
   const int w = w2x2_waves(groups);
   for_each_batch(dev, n, w, [&](int r) { return host[r].n_nodes > 0 ? host[r].n_super : 0; },
                  [&](const GemmBatch& b) {
-                   const bool a1 = half_ahead(P) == 1;
+                   const bool a1 = half_ahead(P, groups, true) == 1;
                    if (w == 1 && a1)
                      k_leaf_gemm_half_w2x2_batch<P, 1, 1><<<grid(b), 64, 0, s>>>(b);
                    else if (w == 1)
