@@ -256,7 +256,11 @@ def main():
     for _ in range(args.warmup):
         solve()
     torch.cuda.synchronize()
+    # Inside the timed steps only the leaf-product launches are bracketed by
+    # events (the roofline's launch durations); each bracket costs host time
+    # between launches.
     sp.profile_reset()
+    sp.profile_phases("gemm")
     sp.profile_enable(True)
     lat, stats = [], None
     torch.cuda.synchronize()
@@ -269,6 +273,16 @@ def main():
     elapsed = time.perf_counter() - t0
     sp.profile_enable(False)
     prof = sp.profile_read()
+    # The per-phase breakdown comes from extra, untimed solves with every
+    # phase bracketed.
+    phase_steps = 2
+    sp.profile_reset()
+    sp.profile_phases()
+    sp.profile_enable(True)
+    for _ in range(phase_steps):
+        solve()
+    sp.profile_enable(False)
+    prof_all = sp.profile_read()
 
     execs = stats["n_exec_total"]
     value = LEAF_FLOP * execs * args.steps / elapsed / 1e9
@@ -315,7 +329,7 @@ def main():
                 "kernel": kname + " (fused SP2 update)",
                 "launches": launches, "mean_launch_ms": round(gemm_ms, 4),
                 "products_per_launch": round(per_launch, 1)}
-    phase_ms = {k: round(v / args.steps, 3) for k, v in prof["ms"].items()}
+    phase_ms = {k: round(v / phase_steps, 3) for k, v in prof_all["ms"].items()}
     # HBM-bound passes: algorithmic bytes over the phase time per solve.
     # Ingest: one read of F and one write of X_0's tiles; output: one read of
     # P's tiles and one write of the dense FP64 P.
@@ -325,7 +339,7 @@ def main():
     passes = {}
     for name, phase, nbytes in (("ingest", "tree", 8 * n * n + tiles0),
                                 ("output", "dense", 8 * n * n + tiles_p)):
-        ms = prof["ms"][phase] / args.steps
+        ms = prof_all["ms"][phase] / phase_steps
         if ms > 0:
             gbs = nbytes / (ms * 1e-3) / 1e9
             passes[name] = {"bytes": nbytes, "ms": round(ms, 4), "gbs": round(gbs, 1),

@@ -349,9 +349,12 @@ const char* spamm_last_error(void);
 const char* spamm_version(void);
 
 /*
- * Kernel timing.  While enabled, every device phase is bracketed by HIP
- * events on the stream it runs on; spamm_profile_read synchronises the
- * device and returns the totals per phase since the last reset.
+ * Kernel timing.  While enabled, every device phase selected by
+ * spamm_profile_phases (all of them unless restricted) is bracketed by
+ * HIP events on the stream it runs on; spamm_profile_read synchronises the
+ * device and returns the totals per phase since the last reset.  Each
+ * bracket costs host time between launches, so a timed run may select only
+ * the phases it reports.
  */
 enum {
     SPAMM_PHASE_TREE = 0,     /* ingest, Gershgorin, leaf norms, tile write */
@@ -370,6 +373,9 @@ typedef struct spamm_profile {
 } spamm_profile;
 
 int spamm_profile_enable(int on);
+/* mask: bit p selects phase p (SPAMM_PHASE_*); 0 or bits >= SPAMM_N_PHASES:
+ * SPAMM_ERR_INVALID_ARG.  Default: every phase. */
+int spamm_profile_phases(unsigned mask);
 int spamm_profile_reset(void);
 int spamm_profile_read(spamm_profile* out);
 

@@ -109,6 +109,7 @@ SIGNATURES = {
     "spamm_last_error": (ctypes.c_char_p, []),
     "spamm_version": (ctypes.c_char_p, []),
     "spamm_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "spamm_profile_phases": (ctypes.c_int, [ctypes.c_uint]),
     "spamm_profile_reset": (ctypes.c_int, []),
     "spamm_profile_read": (ctypes.c_int, [ctypes.POINTER(Profile)]),
     "sp2_footprint_bytes": (ctypes.c_size_t, [_I64, _I32]),
@@ -408,6 +409,15 @@ class Sp2Server:
 
 def profile_enable(on: bool = True):
     _check(load().spamm_profile_enable(int(bool(on))))
+
+
+def profile_phases(*names: str):
+    """Time only the named phases (PHASES); no names: every phase."""
+    unknown = [x for x in names if x not in PHASES]
+    if unknown:
+        raise ValueError(f"unknown phase {unknown[0]!r}; known: {PHASES}")
+    mask = sum(1 << PHASES.index(x) for x in set(names)) if names else (1 << N_PHASES) - 1
+    _check(load().spamm_profile_phases(mask))
 
 
 def profile_reset():

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -45,14 +46,46 @@ void configure_pool(int dev) {
 // ---- kernel timing ----------------------------------------------------------
 
 struct TimedSpan {
-  int phase;
+  int phase, device;
   hipEvent_t a, b;
   int64_t products;
 };
 std::mutex g_prof_mu;
 bool g_prof_on = false;
+unsigned g_prof_mask = (1u << SPAMM_N_PHASES) - 1;
 std::vector<TimedSpan> g_spans;
 spamm_profile g_prof_acc{};
+// Recorded events go back to a per-device pool when read: creating events
+// inside the timed work costs host time between launches.
+std::map<int, std::vector<hipEvent_t>> g_event_pool;
+
+// A timing event of the current device.  Without the system-scope fence a
+// record is a plain timestamp, with no cache write-back between the kernels
+// it separates; the spans are only read after a device synchronisation.
+hipEvent_t take_event(int device) {
+  {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    auto& pool = g_event_pool[device];
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+// Caller holds g_prof_mu.
+void return_span(const TimedSpan& sp) {
+  auto& pool = g_event_pool[sp.device];
+  pool.push_back(sp.a);
+  pool.push_back(sp.b);
+}
 
 // Pinned staging for small device-to-host reads on this thread.  Kept for
 // the life of the process (no HIP call from static destructors).
@@ -286,23 +319,27 @@ void DevBuf::release(hipStream_t s) {
 bool profiling_on() { return g_prof_on; }
 
 PhaseTimer::PhaseTimer(int ph, hipStream_t s, int64_t prod) : phase(ph), stream(s), products(prod) {
-  if (!g_prof_on) return;
-  if (hipEventCreate(&start) != hipSuccess || hipEventRecord(start, s) != hipSuccess) {
+  if (!g_prof_on || !(g_prof_mask >> ph & 1u)) return;
+  start = take_event(current_device());
+  if (start && hipEventRecord(start, s) != hipSuccess) {
     (void)hipGetLastError();
+    (void)hipEventDestroy(start);
     start = nullptr;
   }
 }
 
 PhaseTimer::~PhaseTimer() {
   if (!start) return;
-  hipEvent_t stop = nullptr;
-  if (hipEventCreate(&stop) != hipSuccess || hipEventRecord(stop, stream) != hipSuccess) {
+  const int device = current_device();
+  hipEvent_t stop = take_event(device);
+  if (!stop || hipEventRecord(stop, stream) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipEventDestroy(start);
+    if (stop) (void)hipEventDestroy(stop);
     return;
   }
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  g_spans.push_back(TimedSpan{phase, start, stop, products});
+  g_spans.push_back(TimedSpan{phase, device, start, stop, products});
 }
 
 Error new_matrix(int64_t n, int prec, hipStream_t s, spamm_matrix** out) {
@@ -574,13 +611,17 @@ int spamm_profile_enable(int on) {
   return SPAMM_OK;
 }
 
+int spamm_profile_phases(unsigned mask) {
+  if (mask == 0 || (mask >> SPAMM_N_PHASES) != 0) return fail(SPAMM_ERR_INVALID_ARG, "bad phase mask");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_mask = mask;
+  return SPAMM_OK;
+}
+
 int spamm_profile_reset(void) {
   (void)hipDeviceSynchronize();
   std::lock_guard<std::mutex> lk(g_prof_mu);
-  for (auto& sp : g_spans) {
-    (void)hipEventDestroy(sp.a);
-    (void)hipEventDestroy(sp.b);
-  }
+  for (auto& sp : g_spans) return_span(sp);
   g_spans.clear();
   std::memset(&g_prof_acc, 0, sizeof(g_prof_acc));
   return SPAMM_OK;
@@ -600,8 +641,7 @@ int spamm_profile_read(spamm_profile* out) {
     } else {
       (void)hipGetLastError();
     }
-    (void)hipEventDestroy(sp.a);
-    (void)hipEventDestroy(sp.b);
+    return_span(sp);
   }
   g_spans.clear();
   *out = g_prof_acc;

@@ -89,6 +89,21 @@ def test_sp2_footprint_bound():
     assert sp.sp2_footprint_bytes(100, 9) == 0
 
 
+def test_profile_phase_mask_checks():
+    """Host-only: a phase mask must select at least one of the six phases."""
+    import paper_1403_7458_amd as sp
+    from paper_1403_7458_amd import _lib
+    lib = _lib.load()
+    assert lib.spamm_profile_phases(0) == -1
+    assert lib.spamm_profile_phases(1 << 6) == -1
+    assert b"mask" in lib.spamm_last_error()
+    assert lib.spamm_profile_phases(1 << 3) == 0
+    with pytest.raises(ValueError):
+        sp.profile_phases("gemm", "nope")
+    sp.profile_phases("gemm", "cull")
+    sp.profile_phases()                      # back to every phase
+
+
 def test_sp2_options_defaults_come_from_the_library():
     from paper_1403_7458_amd import _lib
     o = _lib.Sp2Options()
