@@ -187,6 +187,8 @@ struct TopArgs {
   int64_t* nptr;
   int32_t* ks;
   Control* ctl;
+  double* pyr_norms;  // with pyr_top >= 0: first the pyramid tiers pyr_top .. 0
+  int pyr_top;
 };
 
 constexpr int kTopNorms = 1365;  // tiers 0..5: (4^6 - 1) / 3
@@ -206,6 +208,9 @@ __global__ void __launch_bounds__(kTopThreads) k_cull_top(TopArgs g) {
   __shared__ int64_t s_wc[kTopThreads / 64], s_wz[kTopThreads / 64];
   __shared__ double s_e[kTopThreads];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // The single-workgroup top of the operands' pyramid, when the caller left
+  // it to this launch (the operands are then one matrix).
+  if (g.pyr_top >= 0) pyramid_tiers(g.pyr_norms, g.pyr_top);
   Control* ctl = g.ctl;
   const int t0 = g.t0;
   if (tid < kMaxTiers) {
@@ -313,14 +318,15 @@ __device__ inline int64_t parents_in(const Control* ctl, int t, int64_t cap_n, i
 }
 
 // Per chunk: child counts into cnt4, and the chunk's totals (tasks,
-// non-empty children, culled-product sum) into part.
+// non-empty children, culled-product sum, non-empty children off the
+// diagonal) into part.
 __global__ void __launch_bounds__(64 * kWaves) k_cull_count(TierIn in, const double* __restrict__ na,
                                                             const double* __restrict__ nb, int t,
                                                             double tau, Control* ctl,
                                                             int32_t* __restrict__ cnt4,
                                                             int64_t* __restrict__ part,
                                                             uint8_t* __restrict__ bits_out) {
-  __shared__ int64_t s_c[kWaves], s_z[kWaves];
+  __shared__ int64_t s_c[kWaves], s_z[kWaves], s_m[kWaves];
   __shared__ double s_e[kWaves];
   const int64_t P = parents_in(ctl, t, in.cap_nodes, in.cap_tasks);
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->scratch[0] = P;
@@ -328,17 +334,20 @@ __global__ void __launch_bounds__(64 * kWaves) k_cull_count(TierIn in, const dou
   const int64_t ch = (P + kParts - 1) / kParts;
   const int64_t b0 = int64_t(blockIdx.x) * ch, b1 = min(P, b0 + ch);
   const int64_t w = int64_t(2) << t;
-  int64_t c = 0, z = 0;
+  int64_t c = 0, z = 0, m = 0;
   double e = 0.0;
   for (int64_t p = b0 + wave; p < b1; p += kWaves) {
     int32_t cq[4];
     double pe;
     count_parent(in, na, nb, w, tau, p, lane, cq, &pe, bits_out);
     e += pe;
+    const int32_t ij = in.nodes[p];
+    const bool diag = unpack_i(ij) == unpack_j(ij);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       c += cq[q];
       z += cq[q] > 0;
+      m += cq[q] > 0 && !(diag && (q == 0 || q == 3));
     }
     if (lane == 0) {
 #pragma unroll
@@ -348,103 +357,158 @@ __global__ void __launch_bounds__(64 * kWaves) k_cull_count(TierIn in, const dou
   if (lane == 0) {
     s_c[wave] = c;
     s_z[wave] = z;
+    s_m[wave] = m;
     s_e[wave] = e;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int64_t tc = 0, tz = 0;
+    int64_t tc = 0, tz = 0, tm = 0;
     double te = 0.0;
     for (int x = 0; x < kWaves; ++x) {
       tc += s_c[x];
       tz += s_z[x];
+      tm += s_m[x];
       te += s_e[x];
     }
     part[blockIdx.x] = tc;
     part[kParts + blockIdx.x] = tz;
     reinterpret_cast<double*>(part + 2 * kParts)[blockIdx.x] = te;
+    part[3 * kParts + blockIdx.x] = tm;
   }
 }
 
-// Exclusive scan of the chunk totals; tier totals into the control block.
-__global__ void __launch_bounds__(kParts) k_cull_scan(int64_t* __restrict__ part, int t,
-                                                      Control* ctl) {
-  __shared__ int64_t s_wc[kParts / 64], s_wz[kParts / 64];
-  __shared__ double s_e[kParts];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t c = part[tid], z = part[kParts + tid];
-  s_e[tid] = reinterpret_cast<const double*>(part + 2 * kParts)[tid];
-  const int64_t ic = wave_incl_scan(c, lane), iz = wave_incl_scan(z, lane);
-  if (lane == 63) {
-    s_wc[wave] = ic;
-    s_wz[wave] = iz;
-  }
-  __syncthreads();
-  int64_t pc = 0, pz = 0, tc = 0, tz = 0;
-  for (int x = 0; x < kParts / 64; ++x) {
-    if (x < wave) {
-      pc += s_wc[x];
-      pz += s_wz[x];
+__device__ inline int64_t wave_sum_i(int64_t v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Chunk bases and tier totals from the chunk counts, in every workgroup of
+// the write pass (the counts are 32 KiB and stay in L2): for x = tasks,
+// nodes, off-diagonal nodes, the sum over the chunks before `self`
+// (base[x]) and over all chunks (total[x]).  Integer sums: any order gives
+// the same result.
+__device__ inline void chunk_bases(const int64_t* __restrict__ part, int self, int64_t base[3],
+                                   int64_t total[3]) {
+  __shared__ int64_t s_r[6][kWaves];
+  constexpr int kPer = kParts / (64 * kWaves);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int comp[3] = {0, 1, 3};
+  int64_t v[6];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    int64_t before = 0, all = 0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int b = threadIdx.x * kPer + u;
+      const int64_t y = part[comp[x] * kParts + b];
+      all += y;
+      before += b < self ? y : 0;
     }
-    tc += s_wc[x];
-    tz += s_wz[x];
+    v[2 * x] = wave_sum_i(before);
+    v[2 * x + 1] = wave_sum_i(all);
   }
-  part[tid] = pc + ic - c;
-  part[kParts + tid] = pz + iz - z;
+  if (lane == 0)
+#pragma unroll
+    for (int r = 0; r < 6; ++r) s_r[r][wave] = v[r];
+  __syncthreads();
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    base[x] = 0;
+    total[x] = 0;
+    for (int y = 0; y < kWaves; ++y) {
+      base[x] += s_r[2 * x][y];
+      total[x] += s_r[2 * x + 1][y];
+    }
+  }
+}
+
+// Culled-product sum of the tier over the chunks, in the fixed pairwise
+// order of a kParts-leaf tree (one workgroup).
+__device__ inline double chunk_err(const int64_t* __restrict__ part) {
+  __shared__ double s_e[kParts];
+  const double* pe = reinterpret_cast<const double*>(part + 2 * kParts);
+  for (int b = threadIdx.x; b < kParts; b += 64 * kWaves) s_e[b] = pe[b];
+  __syncthreads();
   for (int o = kParts / 2; o > 0; o >>= 1) {
-    if (tid < o) s_e[tid] += s_e[tid + o];
+    for (int b = threadIdx.x; b < o; b += 64 * kWaves) s_e[b] += s_e[b + o];
     __syncthreads();
   }
-  if (tid == 0) {
-    ctl->n_tasks[t + 1] = tc;
-    ctl->n_nodes[t + 1] = tz;
-    ctl->err[t + 1] = s_e[0];
-  }
+  return s_e[0];
 }
 
-// Per chunk: in-chunk exclusive offsets of the child counts, then the
-// children themselves.
+// Per chunk: the chunk's bases (workgroup 0 also stores the tier totals in
+// the control block), in-chunk exclusive offsets of the child counts, then
+// the children themselves.  With `moff` (the leaf tier of symmetric
+// products) also each leaf node's mirror offset: the number of off-diagonal
+// C blocks before it, with their total in ctl->scratch[3].
 __global__ void __launch_bounds__(64 * kWaves) k_cull_write(TierIn in, const double* __restrict__ na,
                                                             const double* __restrict__ nb, int t,
-                                                            double tau, const Control* ctl,
+                                                            double tau, Control* ctl,
                                                             const int32_t* __restrict__ cnt4,
                                                             const int64_t* __restrict__ part,
                                                             int64_t* __restrict__ toff,
                                                             int64_t* __restrict__ noff,
+                                                            int64_t* __restrict__ moff,
                                                             TierOut out) {
-  __shared__ int64_t s_wc[kWaves], s_wz[kWaves];
+  __shared__ int64_t s_wc[kWaves], s_wz[kWaves], s_wm[kWaves];
   const int64_t P = ctl->scratch[0];
-  const int64_t n_out = ctl->n_nodes[t + 1], k_out = ctl->n_tasks[t + 1];
+  int64_t base[3], total[3];
+  chunk_bases(part, blockIdx.x, base, total);
+  const int64_t k_out = total[0], n_out = total[1];
+  if (blockIdx.x == 0) {
+    const double e = chunk_err(part);
+    if (threadIdx.x == 0) {
+      ctl->n_tasks[t + 1] = k_out;
+      ctl->n_nodes[t + 1] = n_out;
+      ctl->err[t + 1] = e;
+      if (moff) ctl->scratch[3] = total[2];
+    }
+  }
   if (n_out > out.cap_nodes || k_out > out.cap_tasks) return;  // resumed with more room
   if (blockIdx.x == 0 && threadIdx.x == 0) out.nptr[n_out] = k_out;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t ch = (P + kParts - 1) / kParts;
   const int64_t b0 = int64_t(blockIdx.x) * ch, b1 = min(P, b0 + ch);
   if (b0 >= b1) return;
-  int64_t base_c = part[blockIdx.x], base_z = part[kParts + blockIdx.x];
+  int64_t base_c = base[0], base_z = base[1], base_m = base[2];
   for (int64_t x0 = 4 * b0; x0 < 4 * b1; x0 += 64 * kWaves) {
     const int64_t x = x0 + threadIdx.x;
     const int32_t v = x < 4 * b1 ? cnt4[x] : 0;
-    const int64_t ic = wave_incl_scan(v, lane), iz = wave_incl_scan(v > 0 ? 1 : 0, lane);
+    const int fz = v > 0 ? 1 : 0;
+    int fm = 0;
+    if (moff && fz) {
+      const int32_t ij = in.nodes[x >> 2];
+      const int q = int(x & 3);
+      fm = !(unpack_i(ij) == unpack_j(ij) && (q == 0 || q == 3));
+    }
+    const int64_t ic = wave_incl_scan(v, lane), iz = wave_incl_scan(fz, lane);
+    const int64_t im = moff ? wave_incl_scan(fm, lane) : 0;
     if (lane == 63) {
       s_wc[wave] = ic;
       s_wz[wave] = iz;
+      s_wm[wave] = im;
     }
     __syncthreads();
-    int64_t pc = 0, pz = 0, tc = 0, tz = 0;
+    int64_t pc = 0, pz = 0, pm = 0, tc = 0, tz = 0, tm = 0;
     for (int y = 0; y < kWaves; ++y) {
       if (y < wave) {
         pc += s_wc[y];
         pz += s_wz[y];
+        pm += s_wm[y];
       }
       tc += s_wc[y];
       tz += s_wz[y];
+      tm += s_wm[y];
     }
     if (x < 4 * b1) {
+      const int64_t node = base_z + pz + iz - fz;
       toff[x] = base_c + pc + ic - v;
-      noff[x] = base_z + pz + iz - (v > 0 ? 1 : 0);
+      noff[x] = node;
+      if (moff && fz) moff[node] = base_m + pm + im - fm;
     }
     base_c += tc;
     base_z += tz;
+    base_m += tm;
     __syncthreads();
   }
   const int64_t w = int64_t(2) << t;
@@ -574,18 +638,21 @@ void expand(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, int t, do
   // The last expansion also keeps each tier-(d-1) triple's 8 pass bits for
   // the leaf products' 2 x 2 block groups.
   uint8_t* bits = t + 1 == a->depth ? static_cast<uint8_t*>(w.bits.p) : nullptr;
+  int64_t* moff = w.upper && t + 1 == a->depth ? static_cast<int64_t*>(w.moff.p) : nullptr;
   k_cull_count<<<kParts, 64 * kWaves, 0, s>>>(in, na, nb, t, tau, ctl,
                                               static_cast<int32_t*>(w.cnt4.p), part, bits);
-  k_cull_scan<<<1, kParts, 0, s>>>(part, t, ctl);
   k_cull_write<<<kParts, 64 * kWaves, 0, s>>>(in, na, nb, t, tau, ctl,
                                               static_cast<const int32_t*>(w.cnt4.p), part,
                                               static_cast<int64_t*>(w.toff.p),
-                                              static_cast<int64_t*>(w.noff.p), tier_out(w, t + 1));
+                                              static_cast<int64_t*>(w.noff.p), moff,
+                                              tier_out(w, t + 1));
 }
 
 void launch_top(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, int t0, double tau,
-                bool want_err, hipStream_t s) {
+                bool want_err, int pyr_top, hipStream_t s) {
   TopArgs g{};
+  g.pyr_norms = a->norms;
+  g.pyr_top = pyr_top;
   g.depth = a->depth;
   g.t0 = t0;
   g.want_err = want_err ? 1 : 0;
@@ -702,7 +769,8 @@ Error mirror_offsets(CullWork& w, int d, hipStream_t s) {
 }  // namespace
 
 Error cull_launch(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
-                  bool want_pairs, hipStream_t s, bool upper) {
+                  bool want_pairs, hipStream_t s, bool upper, int pyr_top) {
+  if (pyr_top >= 0 && a != b) return err(SPAMM_ERR_INVALID_ARG, "deferred pyramid needs A == B");
   const int d = a->depth;
   w.upper = upper;
   const int t_top = std::min(d, kTopTier);
@@ -722,13 +790,17 @@ Error cull_launch(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, dou
     w.depth = d;
   }
   for (int t = 0; t <= d; ++t) SPAMM_TRY(reserve_tier(w, t, s));
-  SPAMM_TRY(w.part.reserve(3 * kParts * sizeof(int64_t), s));
+  SPAMM_TRY(w.part.reserve(4 * kParts * sizeof(int64_t), s));
+  if (upper)
+    SPAMM_TRY(w.moff.grow(size_t(std::max<int64_t>(w.cap_nodes[d], 1)) * sizeof(int64_t), s));
   Control* ctl = w.ctl_dev;
   {
     PhaseTimer timer(SPAMM_PHASE_CULL, s);
-    launch_top(w, a, b, t_top, tau, want_pairs, s);
+    launch_top(w, a, b, t_top, tau, want_pairs, pyr_top, s);
     for (int t = t_top; t < d; ++t) expand(w, a, b, t, tau, s);
-    if (upper) SPAMM_TRY(mirror_offsets(w, d, s));
+    // The leaf tier's write pass stores the mirror offsets; a tree no
+    // deeper than the top tier needs the separate pass.
+    if (upper && t_top == d) SPAMM_TRY(mirror_offsets(w, d, s));
     if (want_pairs)
       k_nonzero_pairs<<<1, 1024, 0, s>>>(a->norms + tier_offset(d), b->norms + tier_offset(d),
                                          a->nb, ctl);
@@ -767,10 +839,11 @@ Error cull_finish(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, dou
       w.cap_tasks[bad + 1] = std::max(w.cap_tasks[bad + 1], ct);
     }
     for (int t = bad - 1; t <= std::min(d, bad + 1); ++t) SPAMM_TRY(reserve_tier(w, t, s));
+    if (w.upper)
+      SPAMM_TRY(w.moff.grow(size_t(std::max<int64_t>(w.cap_nodes[d], 1)) * sizeof(int64_t), s));
     ++out->restarts;
     PhaseTimer timer(SPAMM_PHASE_CULL, s);
     for (int t = bad - 1; t < d; ++t) expand(w, a, b, t, tau, s);
-    if (w.upper) SPAMM_TRY(mirror_offsets(w, d, s));
   }
   const Control& h = *w.ctl_host;
   out->n_cblocks = h.n_nodes[d];

@@ -25,6 +25,26 @@ constexpr int kMaxTiers = SPAMM_MAX_DEPTH + 1;
 
 __host__ __device__ inline int64_t tier_offset(int t) { return ((int64_t(1) << (2 * t)) - 1) / 3; }
 inline int64_t norms_size(int depth) { return tier_offset(depth + 1); }
+
+// Parents of tier t from tier t+1: n^2(parent) = sum of the 4 children's
+// squared norms, added in the order (0,0), (0,1), (1,0), (1,1) (Eq. 3).
+__device__ inline double parent_norm(const double* ch, int64_t w2, int64_t I, int64_t J) {
+  const double a = ch[(2 * I) * w2 + 2 * J], b = ch[(2 * I) * w2 + 2 * J + 1];
+  const double c = ch[(2 * I + 1) * w2 + 2 * J], d = ch[(2 * I + 1) * w2 + 2 * J + 1];
+  return sqrt(a * a + b * b + c * c + d * d);
+}
+
+// Tiers t_top .. 0 of a norm pyramid by one workgroup (each tier reads the
+// one below, written by this workgroup before the barrier).  Every thread
+// of the workgroup calls it.
+__device__ inline void pyramid_tiers(double* __restrict__ norms, int t_top) {
+  for (int t = t_top; t >= 0; --t) {
+    const int64_t w = int64_t(1) << t;
+    for (int64_t x = threadIdx.x; x < w * w; x += blockDim.x)
+      norms[tier_offset(t) + x] = parent_norm(norms + tier_offset(t + 1), 2 * w, x / w, x % w);
+    __syncthreads();
+  }
+}
 // Bytes of one stored 32 x 32 tile: FP64 8 KiB, FP32 4 KiB; 16-bit forms keep
 // the block and its transpose (4 KiB), split forms also the low part (8 KiB).
 inline size_t tile_bytes(int prec) {
@@ -145,7 +165,11 @@ Error compact_nonzero_blocks(spamm_matrix* m, int64_t* count_dev, hipStream_t s)
 void launch_write_tiles(const double* a, int64_t lda, const spamm_matrix* m, const Scale* scale,
                         double* trace_part, hipStream_t s);
 // Tier norms above the leaves (Eq. 3).
-void launch_pyramid(const spamm_matrix* m, hipStream_t s);
+// Tiers depth-1 .. 0 of m's pyramid from its leaf norms.  With leave_top,
+// the tiers that one workgroup computes are left out and their top tier is
+// returned (-1 when none are left): the occlusion pass computes them at its
+// start (cull_launch's pyr_top).
+int launch_pyramid(const spamm_matrix* m, hipStream_t s, bool leave_top = false);
 // Gershgorin bounds, max |F| and the non-finite flag, then the scale of
 // X_0 = (eps_max I - F) / (eps_max - eps_min).
 void launch_gershgorin_scale(const double* f, int64_t n, int64_t ldf, double* row_lo,
@@ -252,9 +276,11 @@ Error run_cull(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double
 // control block to w.ctl_host; after the caller has synchronised `s`,
 // cull_finish regrows and resumes where needed and fills `out`.
 // With `upper` only the C blocks (i, j) with i <= j are kept (products
-// known to be symmetric: the other blocks are their mirrors).
+// known to be symmetric: the other blocks are their mirrors).  With
+// pyr_top >= 0 (a == b) the pass first computes a's pyramid tiers
+// pyr_top .. 0, which launch_pyramid(..., leave_top) left out.
 Error cull_launch(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
-                  bool want_pairs, hipStream_t s, bool upper = false);
+                  bool want_pairs, hipStream_t s, bool upper = false, int pyr_top = -1);
 Error cull_finish(CullWork& w, const spamm_matrix* a, const spamm_matrix* b, double tau,
                   bool want_pairs, hipStream_t s, CullResult* out);
 Error ensure_control(CullWork& w);

@@ -218,7 +218,11 @@ class Sp2Job {
       launch_sp2_rest(opt_.precision, r, s_);
       launch_sp2_reduce(x_->nb, buf_.trace_part, buf_.err_part, nullptr, ctl, s_);
     }
-    launch_pyramid(y_, s_);
+    // The next square's occlusion pass is queued before the one
+    // synchronisation of this iteration, which also brings back t_{n+1}
+    // and e_n; its first launch also finishes X_{n+1}'s pyramid.
+    culled_ = it_ + 1 < opt_.max_iter;
+    const int pyr_top = launch_pyramid(y_, s_, culled_);
     const int it = it_;
     st_.branch[it] = square_ ? 1 : 0;
     st_.trace[it] = t_n_;
@@ -226,15 +230,11 @@ class Sp2Job {
     st_.n_blocks[it] = x_->n_blocks;
     total_exec_ += cr_.n_tasks;
     y_direct_ = cr_.n_cblocks + cr_.n_mirrors;
-    // The next square's occlusion pass is queued before the one
-    // synchronisation of this iteration, which also brings back t_{n+1}
-    // and e_n.
-    culled_ = it + 1 < opt_.max_iter;
     if (!culled_) {
       SPAMM_HIP(hipMemcpyAsync(w_->ctl_host, ctl, sizeof(Control), hipMemcpyDeviceToHost, s_));
       return Error{};
     }
-    SPAMM_TRY(cull_launch(*w_, y_, y_, tau_, false, s_, sym_));
+    SPAMM_TRY(cull_launch(*w_, y_, y_, tau_, false, s_, sym_, pyr_top));
     // The next iterate's map, pyramid and partial sums are cleared now, so
     // that after the synchronisation only the leaf products remain to be
     // queued.  Its buffers are those of X_n, whose last reader (this

@@ -179,14 +179,6 @@ __global__ void __launch_bounds__(256) k_to_dense_half(const void* __restrict__ 
   }
 }
 
-// Parents of tier t from tier t+1: n^2(parent) = sum of the 4 children's
-// squared norms, added in the order (0,0), (0,1), (1,0), (1,1) (Eq. 3).
-__device__ inline double parent_norm(const double* ch, int64_t w2, int64_t I, int64_t J) {
-  const double a = ch[(2 * I) * w2 + 2 * J], b = ch[(2 * I) * w2 + 2 * J + 1];
-  const double c = ch[(2 * I + 1) * w2 + 2 * J], d = ch[(2 * I + 1) * w2 + 2 * J + 1];
-  return sqrt(a * a + b * b + c * c + d * d);
-}
-
 __global__ void k_pyramid_level(double* __restrict__ norms, int t) {
   const int64_t w = int64_t(1) << t;
   const int64_t x = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -195,15 +187,8 @@ __global__ void k_pyramid_level(double* __restrict__ norms, int t) {
   norms[tier_offset(t) + x] = parent_norm(ch, 2 * w, x / w, x % w);
 }
 
-// Tiers t_top .. 0 in one workgroup (each tier reads the one below, written
-// by this workgroup before the barrier).
 __global__ void __launch_bounds__(1024) k_pyramid_top(double* __restrict__ norms, int t_top) {
-  for (int t = t_top; t >= 0; --t) {
-    const int64_t w = int64_t(1) << t;
-    for (int64_t x = threadIdx.x; x < w * w; x += blockDim.x)
-      norms[tier_offset(t) + x] = parent_norm(norms + tier_offset(t + 1), 2 * w, x / w, x % w);
-    __syncthreads();
-  }
+  pyramid_tiers(norms, t_top);
 }
 
 // Gershgorin discs per row: one wave per row.
@@ -438,7 +423,7 @@ void launch_write_tiles(const double* a, int64_t lda, const spamm_matrix* m, con
                                            static_cast<float*>(m->pool), scale, trace_part);
 }
 
-void launch_pyramid(const spamm_matrix* m, hipStream_t s) {
+int launch_pyramid(const spamm_matrix* m, hipStream_t s, bool leave_top) {
   PhaseTimer timer(SPAMM_PHASE_PYRAMID, s);
   // Tiers of up to 4^6 nodes go to the single-workgroup kernel (4 nodes per
   // thread): one launch instead of one per tier for trees of depth <= 7.
@@ -447,7 +432,10 @@ void launch_pyramid(const spamm_matrix* m, hipStream_t s) {
     const int64_t w2 = int64_t(1) << (2 * t);
     k_pyramid_level<<<grid_for(w2, 256), 256, 0, s>>>(m->norms, t);
   }
-  if (t >= 0) k_pyramid_top<<<1, 1024, 0, s>>>(m->norms, t);
+  if (t < 0) return -1;
+  if (leave_top) return t;
+  k_pyramid_top<<<1, 1024, 0, s>>>(m->norms, t);
+  return -1;
 }
 
 void launch_gershgorin_scale(const double* f, int64_t n, int64_t ldf, double* row_lo,
