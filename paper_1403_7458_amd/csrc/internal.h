@@ -26,6 +26,15 @@ constexpr int kMaxTiers = SPAMM_MAX_DEPTH + 1;
 __host__ __device__ inline int64_t tier_offset(int t) { return ((int64_t(1) << (2 * t)) - 1) / 3; }
 inline int64_t norms_size(int depth) { return tier_offset(depth + 1); }
 
+// Column-quad order of an FP32 32 x 32 tile, the operand layout of the
+// 2 x 2 leaf kernels: element (r, c) at ((r % 16) / 4 * 64 + r / 16 * 32 + c)
+// * 4 + r % 4, so that 16-byte load q of lane l = 32 kk + c holds rows
+// 16 kk + 4 q .. 16 kk + 4 q + 3 of column c, and each load of a wave reads
+// 1 KiB contiguously.
+__host__ __device__ inline int colq_index(int r, int c) {
+  return (((r & 15) >> 2) * 64 + (r >> 4) * 32 + c) * 4 + (r & 3);
+}
+
 // Parents of tier t from tier t+1: n^2(parent) = sum of the 4 children's
 // squared norms, added in the order (0,0), (0,1), (1,0), (1,1) (Eq. 3).
 __device__ inline double parent_norm(const double* ch, int64_t w2, int64_t I, int64_t J) {
@@ -131,6 +140,7 @@ struct spamm_matrix {
   double* norms = nullptr;
   double frob = 0.0;
   bool owns = true;  // false: the buffers belong to a workspace (SP2 iterates)
+  void* colq = nullptr;  // FP32 SP2 operands: column-quad copy of the pool (never owned)
 };
 
 namespace spamm {
@@ -340,6 +350,12 @@ struct GemmArgs {
   // (j, i) in slot n_nodes + moff[node], with the same norm and partials.
   int sym;
   const int64_t* moff;
+  // FP32 symmetric squares: the operands' column-quad copy (colq_a, see
+  // colq_index; A_ik is read as the columns of its stored transpose (k, i)),
+  // and where C's column-quad copy goes (colq_c, with its mirror's).  Null:
+  // operands are read from the row-major pools.
+  const void* colq_a;
+  void* colq_c;
 };
 // Slot of the mirror of C block `node` = (i, j), or -1.
 __device__ inline int64_t mirror_slot(const GemmArgs& g, int64_t node, int i, int j) {
@@ -453,8 +469,12 @@ struct RestArgs {
   double* trace_part;
   double* err_part;
   int64_t* counter;      // appended blocks
+  const void* colq_x;    // FP32: column-quad copies of X_n and of the output, or null
+  void* colq_out;
 };
 void launch_sp2_rest(int prec, const RestArgs& r, hipStream_t s);
+// Column-quad copies (colq_index) of n FP32 row-major tiles.
+void launch_tiles_to_colq(const void* pool, int64_t n, void* colq, hipStream_t s);
 void launch_sp2_rest_half(int prec, const RestArgs& r, hipStream_t s);
 // map(-1), leaf norms, err_part (nb*nb), trace_part (nb) and the counter
 // cleared for one SP2 iteration.
@@ -510,7 +530,7 @@ struct DenseIn {
 // slot coordinates), reused from iteration to iteration: X_{n+1} takes the
 // buffers X_{n-1} held.
 struct IterBuf {
-  DevBuf map, norms, pool, coords;
+  DevBuf map, norms, pool, coords;  // pool: the tiles, then their column-quad copies if any
   void release(hipStream_t s) {
     map.release(s);
     norms.release(s);

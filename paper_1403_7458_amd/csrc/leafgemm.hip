@@ -395,6 +395,30 @@ __device__ inline void load_w2x2(const float* __restrict__ pa, const float* __re
   }
 }
 
+// The same operands from the column-quad copies (colq_index): A_ik as the
+// columns of its stored transpose (k, i) (symmetric squares), B_kj as the
+// columns of (k, j); every load of the wave reads 1 KiB contiguously.
+__device__ inline void load_w2x2_colq(const float* __restrict__ cq, const int32_t (&sl)[4], int lane,
+                                      W2x2Frag& f) {
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    if (sl[u] >= 0) {
+      const v4f* at = reinterpret_cast<const v4f*>(cq + int64_t(sl[u]) * kLeaf2) + lane;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) f.a[u][q] = at[q * 64];
+    }
+    if (sl[2 + u] >= 0) {
+      const v4f* bt = reinterpret_cast<const v4f*>(cq + int64_t(sl[2 + u]) * kLeaf2) + lane;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const v4f v = bt[q * 64];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) f.b[u][4 * q + e] = v[e];
+      }
+    }
+  }
+}
+
 __device__ inline void mma_pair(const v4f (&a)[4], const float (&b)[16], v16f& acc) {
 #pragma unroll
   for (int s = 0; s < 16; ++s)
@@ -420,9 +444,17 @@ __device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
   const int I = unpack_i(IJ), J = unpack_j(IJ);
   const float* pa = static_cast<const float*>(g.pool_a);
   const float* pb = static_cast<const float*>(g.pool_b);
+  const float* cq = static_cast<const float*>(g.colq_a);
   const int64_t e0 = uniform(g.sup_nptr[p]), e1 = uniform(g.sup_nptr[p + 1]);
   v16f acc[4] = {};
   W2x2Frag cur, nxt;
+  // Operands from the row-major pools or from the column-quad copy.
+  auto load = [&](const int32_t (&sl)[4], W2x2Frag& f) {
+    if (cq)
+      load_w2x2_colq(cq, sl, lane, f);
+    else
+      load_w2x2(pa, pb, sl, lane, f);
+  };
   for (int64_t eb = e0; eb < e1; eb += kWBatch) {
     // Steps of this batch: lane l takes entry l / 2, c = l % 2.
     int32_t mask = 0, sl[4] = {-1, -1, -1, -1};
@@ -432,8 +464,11 @@ __device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
       const int bits = g.sup_bits[e];
       for (int q = 0; q < 4; ++q) mask |= ((bits >> (2 * q + c)) & 1) << q;
       const int k = 2 * g.sup_ks[e] + c;
-      if (mask & 0x3) sl[0] = g.map_a[int64_t(2 * I) * g.nb + k];
-      if (mask & 0xC) sl[1] = g.map_a[int64_t(2 * I + 1) * g.nb + k];
+      // Column-quad operands: A_ik as its transpose, the stored block (k, i).
+      if (mask & 0x3)
+        sl[0] = cq ? g.map_a[int64_t(k) * g.nb + 2 * I] : g.map_a[int64_t(2 * I) * g.nb + k];
+      if (mask & 0xC)
+        sl[1] = cq ? g.map_a[int64_t(k) * g.nb + 2 * I + 1] : g.map_a[int64_t(2 * I + 1) * g.nb + k];
       if (mask & 0x5) sl[2] = g.map_b[int64_t(k) * g.nb + 2 * J];
       if (mask & 0xA) sl[3] = g.map_b[int64_t(k) * g.nb + 2 * J + 1];
     }
@@ -457,23 +492,23 @@ __device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
       for (int x = 0; x < n_steps; ++x) {
         int32_t s0[4];
         slots(x, s0);
-        load_w2x2(pa, pb, s0, lane, cur);
+        load(s0, cur);
         mma_w2x2(cur, step_mask(x), acc);
       }
     } else if (n_steps > 0) {
       int32_t s0[4];
       slots(0, s0);
-      load_w2x2(pa, pb, s0, lane, cur);
+      load(s0, cur);
       int x = 0;
       for (; x + 2 < n_steps; x += 2) {
         int32_t s1[4], s2[4];
         slots(x + 1, s1);
-        load_w2x2(pa, pb, s1, lane, nxt);
+        load(s1, nxt);
         __builtin_amdgcn_sched_barrier(0);
         mma_w2x2(cur, step_mask(x), acc);
         __builtin_amdgcn_sched_barrier(0);
         slots(x + 2, s2);
-        load_w2x2(pa, pb, s2, lane, cur);
+        load(s2, cur);
         __builtin_amdgcn_sched_barrier(0);
         mma_w2x2(nxt, step_mask(x + 1), acc);
         __builtin_amdgcn_sched_barrier(0);
@@ -481,7 +516,7 @@ __device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
       if (x + 1 < n_steps) {
         int32_t s1[4];
         slots(x + 1, s1);
-        load_w2x2(pa, pb, s1, lane, nxt);
+        load(s1, nxt);
         __builtin_amdgcn_sched_barrier(0);
         mma_w2x2(cur, step_mask(x), acc);
         mma_w2x2(nxt, step_mask(x + 1), acc);
@@ -505,6 +540,9 @@ __device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
       const int32_t sx = g.map_x[int64_t(i) * g.nb + j];
       if (sx >= 0) xt = static_cast<const float*>(g.pool_x) + int64_t(sx) * kLeaf2;
     }
+    // Column-quad copies of the block and of its mirror.
+    float* oq = g.colq_c ? static_cast<float*>(g.colq_c) + node * kLeaf2 : nullptr;
+    float* omq = g.colq_c && ms >= 0 ? static_cast<float*>(g.colq_c) + ms * kLeaf2 : nullptr;
     Epi<float> e;
     v4f m4;
 #pragma unroll
@@ -513,10 +551,14 @@ __device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
       const float x = xt ? xt[row * kLeaf + col] : 0.0f;
       const float v = e.apply(a[r], x, g.sp2, g.square, i == j && row == col);
       out[row * kLeaf + col] = v;
-      // The mirror's row `col` holds this lane's 4 consecutive rows.
+      if (omq) omq[colq_index(col, row)] = v;
+      // The mirror's row `col` holds this lane's 4 consecutive rows, and so
+      // does the block's own column-quad copy.
       m4[r & 3] = v;
-      if ((r & 3) == 3 && outm)
-        *reinterpret_cast<v4f*>(outm + col * kLeaf + (r >> 2) * 8 + kk * 4) = m4;
+      if ((r & 3) == 3) {
+        if (outm) *reinterpret_cast<v4f*>(outm + col * kLeaf + (r >> 2) * 8 + kk * 4) = m4;
+        if (oq) *reinterpret_cast<v4f*>(oq + colq_index(row - 3, col)) = m4;
+      }
     }
     e.finish(g, node, pack_ij(i, j), lane, ms);
   };
@@ -842,6 +884,13 @@ __global__ void __launch_bounds__(256) k_sp2_rest(RestArgs r) {
     nrm += double(w) * double(w);
     if (i == j && (e_ >> 5) == (e_ & 31)) tr += double(w);
   }
+  // 2 X_n elementwise: the column-quad copy from X_n's, position by position.
+  if (r.colq_out) {
+    const T* xq = static_cast<const T*>(r.colq_x) + s * kLeaf2;
+    T* oq = static_cast<T*>(r.colq_out) + slot * kLeaf2;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) oq[q * 64 + lane] = T(2) * xq[q * 64 + lane];
+  }
   nrm = wave_sum(nrm);
   if (i == j) tr = wave_sum(tr);
   if (lane == 0) {
@@ -849,6 +898,24 @@ __global__ void __launch_bounds__(256) k_sp2_rest(RestArgs r) {
     r.coords_out[slot] = ij;
     r.norm_out[cell] = sqrt(nrm);
     if (i == j) r.trace_part[i] = tr;
+  }
+}
+
+// Column-quad copies of row-major FP32 tiles: one wave per tile, each lane
+// writing 16 consecutive floats of the copy.
+__global__ void __launch_bounds__(256) k_tiles_to_colq(const float* __restrict__ pool, int64_t n,
+                                                       float* __restrict__ colq) {
+  const int lane = threadIdx.x & 63;
+  const int64_t t = int64_t(blockIdx.x) * kWaves + (threadIdx.x >> 6);
+  if (t >= n) return;
+  const float* src = pool + t * kLeaf2;
+  float* dst = colq + t * kLeaf2;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int x = q * 64 + lane;  // position in the copy
+    const int quad = x >> 2, e = x & 3;
+    const int c = quad & 31, r = ((quad >> 6) << 2) + (((quad >> 5) & 1) << 4) + e;
+    dst[x] = src[r * kLeaf + c];
   }
 }
 
@@ -1035,6 +1102,12 @@ void launch_sp2_rest(int prec, const RestArgs& r, hipStream_t s) {
     k_sp2_rest<double><<<grid, 64 * kWaves, 0, s>>>(r);
   else
     k_sp2_rest<float><<<grid, 64 * kWaves, 0, s>>>(r);
+}
+
+void launch_tiles_to_colq(const void* pool, int64_t n, void* colq, hipStream_t s) {
+  if (n <= 0) return;
+  k_tiles_to_colq<<<unsigned((n + kWaves - 1) / kWaves), 64 * kWaves, 0, s>>>(
+      static_cast<const float*>(pool), n, static_cast<float*>(colq));
 }
 
 void launch_sp2_prepare(int32_t* map, double* norm_leaf, double* err_part, int nb,

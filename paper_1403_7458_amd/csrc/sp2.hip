@@ -48,12 +48,14 @@ struct Sp2Buffers {
   int64_t* cnt = nullptr;
   double* trace_part = nullptr;
   double* err_part = nullptr;
+  float* colq0 = nullptr;  // column-quad copy of X_0's tiles (FP32 symmetric squares)
   ~Sp2Buffers() {
     dev_free(row, s);
     dev_free(scale, s);
     dev_free(cnt, s);
     dev_free(trace_part, s);
     dev_free(err_part, s);
+    dev_free(colq0, s);
   }
 };
 
@@ -130,6 +132,16 @@ class Sp2Job {
     sym_ = opt_.symmetric && sh_.max_asym == 0.0 &&
            !(opt_.precision == SPAMM_FP32 && (choice == kLeaf2x2 || choice == kLeaf4x4));
     st_.symmetric = sym_ ? 1 : 0;
+    // FP32 symmetric squares on the 2 x 2 kernels read their operands from
+    // column-quad copies of the tiles (coalesced loads); every iterate
+    // carries one, written next to its row-major tiles.
+    colq_ = sym_ && opt_.precision == SPAMM_FP32 && x_->depth >= 1 &&
+            (choice == kLeafW2x2 || choice == kLeafW2x2s);
+    if (colq_) {
+      SPAMM_TRY(dev_alloc_n(&buf_.colq0, std::max<int64_t>(x_->n_blocks, 1) * kLeaf2, s_));
+      launch_tiles_to_colq(x_->pool, x_->n_blocks, buf_.colq0, s_);
+      x_->colq = buf_.colq0;
+    }
     launch_sp2_reduce(x_->nb, buf_.trace_part, nullptr, nullptr, w_->ctl_dev, s_);
     return cull_launch(*w_, x_, x_, tau_, false, s_, sym_);
   }
@@ -193,6 +205,8 @@ class Sp2Job {
     g->overflow = reinterpret_cast<int32_t*>(&ctl->scratch[2]);
     g->sym = sym_ ? 1 : 0;
     g->moff = cr_.moff;
+    g->colq_a = x_->colq;
+    g->colq_c = y_->colq;
     *products = cr_.n_tasks;
     return Error{};
   }
@@ -215,6 +229,8 @@ class Sp2Job {
       r.trace_part = buf_.trace_part;
       r.err_part = buf_.err_part;
       r.counter = &ctl->scratch[1];
+      r.colq_x = x_->colq;
+      r.colq_out = y_->colq;
       launch_sp2_rest(opt_.precision, r, s_);
       launch_sp2_reduce(x_->nb, buf_.trace_part, buf_.err_part, nullptr, ctl, s_);
     }
@@ -306,8 +322,9 @@ class Sp2Job {
     const int64_t rb = (n_ + kLeaf - 1) / kLeaf, most = 2 * rb * rb;
     SPAMM_TRY(b.map.grow(size_t(nb) * nb * sizeof(int32_t), s_));
     SPAMM_TRY(b.norms.grow(size_t(norms_size(depth)) * sizeof(double), s_));
-    SPAMM_TRY(b.pool.grow(size_t(cap) * tile_bytes(opt_.precision), s_,
-                          size_t(most) * tile_bytes(opt_.precision)));
+    // With column-quad copies the pool holds cap tiles, then their copies.
+    const size_t tb = tile_bytes(opt_.precision) * (colq_ ? 2 : 1);
+    SPAMM_TRY(b.pool.grow(size_t(cap) * tb, s_, size_t(most) * tb));
     SPAMM_TRY(b.coords.grow(size_t(cap) * sizeof(int32_t), s_, size_t(most) * sizeof(int32_t)));
     spamm_matrix* m = new spamm_matrix();
     m->n = n_;
@@ -323,6 +340,8 @@ class Sp2Job {
     m->coords = static_cast<int32_t*>(b.coords.p);
     m->norms = static_cast<double*>(b.norms.p);
     m->owns = false;
+    m->colq = colq_ ? static_cast<char*>(b.pool.p) + size_t(cap) * tile_bytes(opt_.precision)
+                    : nullptr;
     *out = m;
     return Error{};
   }
@@ -344,6 +363,7 @@ class Sp2Job {
   int it_ = 0;
   int stop_ = SP2_STOP_MAX_ITER;
   bool done_ = false, square_ = false, culled_ = false, sym_ = false, prepared_ = false;
+  bool colq_ = false;
   int64_t total_exec_ = 0, y_direct_ = 0;
 };
 
@@ -414,7 +434,11 @@ size_t footprint_bytes(int64_t n, int prec) {
   }
   const double rb = double((n + kLeaf - 1) / kLeaf);
   const double cells = double(nb) * nb;
-  double b = 4.0 * rb * rb * (double(tile_bytes(prec)) + 4.0);
+  // FP32 iterates also hold column-quad copies of their tiles, and X_0 one
+  // of its own.
+  const double tb = double(tile_bytes(prec)) * (prec == SPAMM_FP32 ? 2.0 : 1.0);
+  double b = 4.0 * rb * rb * (tb + 4.0);
+  if (prec == SPAMM_FP32) b += rb * rb * double(tile_bytes(prec));
   b += 2.0 * (cells * 8.0 + double(norms_size(depth)) * 8.0);
   b += 2.0 * double(n) * double(n) * 8.0;
   b += cells * 8.0 + double(nb) * 8.0 + 3.0 * double(n) * 8.0;

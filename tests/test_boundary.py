@@ -84,7 +84,10 @@ def test_sp2_footprint_bound():
             assert b >= 3 * rb * rb * tb + 2 * n * n * 8
             assert b >= last
             last = b
-    assert sp.sp2_footprint_bytes(3750, "fp64") > sp.sp2_footprint_bytes(3750, "fp32")
+    # FP64 blocks are 8 KiB, BF16 ones 4 KiB; FP32 iterates hold 4 KiB blocks
+    # and a column-quad copy of each.
+    assert sp.sp2_footprint_bytes(3750, "fp64") > sp.sp2_footprint_bytes(3750, "bf16")
+    assert sp.sp2_footprint_bytes(3750, "fp32") > sp.sp2_footprint_bytes(3750, "fp64")
     assert sp.sp2_footprint_bytes(0, "fp32") == 0
     assert sp.sp2_footprint_bytes(100, 9) == 0
 
