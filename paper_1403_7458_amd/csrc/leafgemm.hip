@@ -437,20 +437,22 @@ constexpr int kWBatch = 32;            // list entries per slot batch (64 steps)
 // kAhead: operand sets in flight per wave (2: the next step's loads overlap
 // the current step's products; 1: other waves hide the latency).
 // Group p of g; tab: the wave's LDS step table (mask, 4 slots per step).
-template <int kAhead>
+// kColq: operands from the column-quad copy (1), the row-major pools (0),
+// or as g.colq_a says (2, batched launches of mixed products).
+template <int kAhead, int kColq>
 __device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
                                          int32_t (*tab)[2 * kWBatch]) {
   const int32_t IJ = uniform(g.sup_nodes[p]);
   const int I = unpack_i(IJ), J = unpack_j(IJ);
   const float* pa = static_cast<const float*>(g.pool_a);
   const float* pb = static_cast<const float*>(g.pool_b);
-  const float* cq = static_cast<const float*>(g.colq_a);
+  const float* cq = kColq == 0 ? nullptr : static_cast<const float*>(g.colq_a);
   const int64_t e0 = uniform(g.sup_nptr[p]), e1 = uniform(g.sup_nptr[p + 1]);
   v16f acc[4] = {};
   W2x2Frag cur, nxt;
   // Operands from the row-major pools or from the column-quad copy.
   auto load = [&](const int32_t (&sl)[4], W2x2Frag& f) {
-    if (cq)
+    if (kColq == 1 || (kColq == 2 && cq))
       load_w2x2_colq(cq, sl, lane, f);
     else
       load_w2x2(pa, pb, sl, lane, f);
@@ -569,13 +571,13 @@ __device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
 }
 
 // kW: waves (2 x 2 groups) per workgroup.
-template <int kAhead, int kW>
+template <int kAhead, int kW, int kColq>
 __global__ void __launch_bounds__(64 * kW) k_leaf_gemm_f32_w2x2(GemmArgs g) {
   __shared__ int32_t s_tab[kW][5][2 * kWBatch];
   const int wave = threadIdx.x >> 6;
   const int64_t p = uniform(xcd_contiguous_block() * kW + wave);
   if (p >= g.n_super) return;
-  f32_w2x2<kAhead>(g, p, threadIdx.x & 63, s_tab[wave]);
+  f32_w2x2<kAhead, kColq>(g, p, threadIdx.x & 63, s_tab[wave]);
 }
 
 template <int kAhead, int kW>
@@ -585,7 +587,7 @@ __global__ void __launch_bounds__(64 * kW) k_leaf_gemm_f32_w2x2_batch(GemmBatch 
   int64_t p = 0;
   const GemmArgs* g = batch_locate(b, wave, p);
   if (!g) return;
-  f32_w2x2<kAhead>(*g, p, threadIdx.x & 63, s_tab[wave]);
+  f32_w2x2<kAhead, 2>(*g, p, threadIdx.x & 63, s_tab[wave]);
 }
 
 // ---- FP32 leaf products on 4 x 4 groups of C blocks --------------------------
@@ -999,15 +1001,23 @@ int w2x2_waves(int64_t groups) {
   return groups >= kManyGroups ? 4 : 1;
 }
 
-template <int kAhead>
-static void launch_w2x2_a(int waves, const GemmArgs& g, hipStream_t s) {
+template <int kAhead, int kColq>
+static void launch_w2x2_c(int waves, const GemmArgs& g, hipStream_t s) {
   const unsigned grid = unsigned((g.n_super + waves - 1) / waves);
   if (waves == 1)
-    k_leaf_gemm_f32_w2x2<kAhead, 1><<<grid, 64, 0, s>>>(g);
+    k_leaf_gemm_f32_w2x2<kAhead, 1, kColq><<<grid, 64, 0, s>>>(g);
   else if (waves == 2)
-    k_leaf_gemm_f32_w2x2<kAhead, 2><<<grid, 128, 0, s>>>(g);
+    k_leaf_gemm_f32_w2x2<kAhead, 2, kColq><<<grid, 128, 0, s>>>(g);
   else
-    k_leaf_gemm_f32_w2x2<kAhead, 4><<<grid, 256, 0, s>>>(g);
+    k_leaf_gemm_f32_w2x2<kAhead, 4, kColq><<<grid, 256, 0, s>>>(g);
+}
+
+template <int kAhead>
+static void launch_w2x2_a(int waves, const GemmArgs& g, hipStream_t s) {
+  if (g.colq_a)
+    launch_w2x2_c<kAhead, 1>(waves, g, s);
+  else
+    launch_w2x2_c<kAhead, 0>(waves, g, s);
 }
 
 static void launch_w2x2(int ahead, int waves, const GemmArgs& g, hipStream_t s) {
