@@ -439,9 +439,12 @@ constexpr int kWBatch = 32;            // list entries per slot batch (64 steps)
 // Group p of g; tab: the wave's LDS step table (mask, 4 slots per step).
 // kColq: operands from the column-quad copy (1), the row-major pools (0),
 // or as g.colq_a says (2, batched launches of mixed products).
+// stage (kColq != 0): the wave's LDS tile, through which each mirror is
+// written transposed with coalesced stores.
+constexpr int kStagePitch = 33;
 template <int kAhead, int kColq>
 __device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
-                                         int32_t (*tab)[2 * kWBatch]) {
+                                         int32_t (*tab)[2 * kWBatch], float* stage) {
   const int32_t IJ = uniform(g.sup_nodes[p]);
   const int I = unpack_i(IJ), J = unpack_j(IJ);
   const float* pa = static_cast<const float*>(g.pool_a);
@@ -542,9 +545,10 @@ __device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
       const int32_t sx = g.map_x[int64_t(i) * g.nb + j];
       if (sx >= 0) xt = static_cast<const float*>(g.pool_x) + int64_t(sx) * kLeaf2;
     }
-    // Column-quad copies of the block and of its mirror.
-    float* oq = g.colq_c ? static_cast<float*>(g.colq_c) + node * kLeaf2 : nullptr;
-    float* omq = g.colq_c && ms >= 0 ? static_cast<float*>(g.colq_c) + ms * kLeaf2 : nullptr;
+    // Column-quad copies of the block and of its mirror; with them the
+    // mirror goes through the LDS tile.
+    float* oq = kColq != 0 && g.colq_c ? static_cast<float*>(g.colq_c) + node * kLeaf2 : nullptr;
+    float* omq = oq && ms >= 0 ? static_cast<float*>(g.colq_c) + ms * kLeaf2 : nullptr;
     Epi<float> e;
     v4f m4;
 #pragma unroll
@@ -553,14 +557,36 @@ __device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
       const float x = xt ? xt[row * kLeaf + col] : 0.0f;
       const float v = e.apply(a[r], x, g.sp2, g.square, i == j && row == col);
       out[row * kLeaf + col] = v;
-      if (omq) omq[colq_index(col, row)] = v;
+      if (omq) stage[row * kStagePitch + col] = v;
       // The mirror's row `col` holds this lane's 4 consecutive rows, and so
       // does the block's own column-quad copy.
       m4[r & 3] = v;
       if ((r & 3) == 3) {
-        if (outm) *reinterpret_cast<v4f*>(outm + col * kLeaf + (r >> 2) * 8 + kk * 4) = m4;
+        if (outm && !omq)
+          *reinterpret_cast<v4f*>(outm + col * kLeaf + (r >> 2) * 8 + kk * 4) = m4;
         if (oq) *reinterpret_cast<v4f*>(oq + colq_index(row - 3, col)) = m4;
       }
+    }
+    if (omq) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // Mirror M = C^T: row 2t + kk of M is column 2t + kk of C; its
+      // column-quad load q of lane (kk, c) holds C(c, 16 kk + 4 q .. + 3).
+#pragma unroll
+      for (int t = 0; t < 16; ++t) {
+        const int rm = 2 * t + kk;
+        outm[rm * kLeaf + col] = stage[col * kStagePitch + rm];
+      }
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4) {
+        v4f w;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) w[u] = stage[col * kStagePitch + 16 * kk + 4 * q4 + u];
+        *reinterpret_cast<v4f*>(omq + (q4 * 64 + lane) * 4) = w;
+      }
+      // Every lane's reads precede the next block's writes.
+      __builtin_amdgcn_wave_barrier();
     }
     e.finish(g, node, pack_ij(i, j), lane, ms);
   };
@@ -574,20 +600,22 @@ __device__ __forceinline__ void f32_w2x2(const GemmArgs& g, int64_t p, int lane,
 template <int kAhead, int kW, int kColq>
 __global__ void __launch_bounds__(64 * kW) k_leaf_gemm_f32_w2x2(GemmArgs g) {
   __shared__ int32_t s_tab[kW][5][2 * kWBatch];
+  __shared__ float s_stage[kW][kColq != 0 ? kLeaf * kStagePitch : 1];
   const int wave = threadIdx.x >> 6;
   const int64_t p = uniform(xcd_contiguous_block() * kW + wave);
   if (p >= g.n_super) return;
-  f32_w2x2<kAhead, kColq>(g, p, threadIdx.x & 63, s_tab[wave]);
+  f32_w2x2<kAhead, kColq>(g, p, threadIdx.x & 63, s_tab[wave], s_stage[wave]);
 }
 
 template <int kAhead, int kW>
 __global__ void __launch_bounds__(64 * kW) k_leaf_gemm_f32_w2x2_batch(GemmBatch b) {
   __shared__ int32_t s_tab[kW][5][2 * kWBatch];
+  __shared__ float s_stage[kW][kLeaf * kStagePitch];
   const int wave = threadIdx.x >> 6;
   int64_t p = 0;
   const GemmArgs* g = batch_locate(b, wave, p);
   if (!g) return;
-  f32_w2x2<kAhead, 2>(*g, p, threadIdx.x & 63, s_tab[wave]);
+  f32_w2x2<kAhead, 2>(*g, p, threadIdx.x & 63, s_tab[wave], s_stage[wave]);
 }
 
 // ---- FP32 leaf products on 4 x 4 groups of C blocks --------------------------
