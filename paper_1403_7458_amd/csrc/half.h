@@ -1,9 +1,10 @@
 // 16-bit tile formats of the reduced-precision forms.
 //
-// A slot of a BF16 / FP16 matrix holds 1024 16-bit values of the block,
-// row-major (part 0), then the same values transposed (part 1), so that
-// both the A role (rows of A_ik) and the B role (columns of B_kj) of a leaf
-// product read one contiguous 32-byte run per lane.  The split forms
+// A slot of a BF16 / FP16 matrix holds 1024 16-bit values of the block
+// (part 0), then the same values transposed (part 1), each part in the
+// operand order of the leaf kernels (half_idx), so that both the A role
+// (rows of A_ik) and the B role (columns of B_kj) of a leaf product read
+// 1 KiB contiguously per load of a wave.  The split forms
 // (BF16X3, FP16X3) add a low part and its transpose (parts 2 and 3):
 //   x = hi + lo * 2^-L,  hi = round16(x),  lo = round16((x - hi) * 2^L),
 // L = 0 for BF16 (its exponent range covers the residual) and L = 11 for
@@ -99,5 +100,16 @@ __device__ inline float decode_half_f(typename Half<P>::T hi, typename Half<P>::
 
 // Element offsets of the parts of a 16-bit tile.
 __host__ __device__ constexpr int64_t half_part(int part) { return int64_t(part) * kLeaf2; }
+
+// Position of element (r, c) inside a part: the 16-byte operand of lane
+// l = 32 kk + r for MFMA step s (k = 16 kk + 8 s .. + 7) is chunk 64 s + l,
+// so each step's operand load of a wave reads 1 KiB contiguously.
+__host__ __device__ constexpr int half_idx(int r, int c) {
+  return (((c & 15) >> 3) * 64 + (c >> 4) * 32 + r) * 8 + (c & 7);
+}
+// Whether position x of a part holds a diagonal element (r == c).
+__host__ __device__ constexpr bool half_idx_diag(int x) {
+  return ((x >> 3) & 31) == (((x >> 8) & 1) << 4) + ((x >> 9) << 3) + (x & 7);
+}
 
 }  // namespace spamm

@@ -40,14 +40,14 @@ struct HFrag {
 template <int P>
 __device__ inline void load_frag(const typename Half<P>::T* tile, int part, int lane, HFrag<P>& f) {
   typedef typename Half<P>::V V;
-  const int m = lane & 31, kk = lane >> 5;
-  const V* p = reinterpret_cast<const V*>(tile + half_part(part) + m * kLeaf + 16 * kk);
+  // Chunk 64 s + lane of the part (half_idx).
+  const V* p = reinterpret_cast<const V*>(tile + half_part(part)) + lane;
   f.hi[0] = p[0];
-  f.hi[1] = p[1];
+  f.hi[1] = p[64];
   if (is_split(P)) {
-    const V* q = reinterpret_cast<const V*>(tile + half_part(part + 2) + m * kLeaf + 16 * kk);
+    const V* q = reinterpret_cast<const V*>(tile + half_part(part + 2)) + lane;
     f.lo[0] = q[0];
-    f.lo[1] = q[1];
+    f.lo[1] = q[64];
   }
 }
 
@@ -133,8 +133,8 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int64_t node, int i,
     float v = c;
     if (g.sp2) {
       const float x =
-          xt ? decode_half_f<P>(xt[row * kLeaf + col],
-                                is_split(P) ? xt[half_part(2) + row * kLeaf + col] : T(0.0f))
+          xt ? decode_half_f<P>(xt[half_idx(row, col)],
+                                is_split(P) ? xt[half_part(2) + half_idx(row, col)] : T(0.0f))
              : 0.0f;
       v = g.square ? c : 2.0f * x - c;
       const double d = double(c) - double(x);
@@ -143,18 +143,19 @@ __device__ __forceinline__ void epilogue(const GemmArgs& g, int64_t node, int i,
     over |= !(fabsf(v) <= float(half_max(P)));
     T hi, lo;
     encode_half_f<P>(v, hi, lo);
-    out[row * kLeaf + col] = hi;
-    out[half_part(1) + col * kLeaf + row] = hi;
+    const int rc = half_idx(row, col), cr = half_idx(col, row);
+    out[rc] = hi;
+    out[half_part(1) + cr] = hi;
     if (is_split(P)) {
-      out[half_part(2) + row * kLeaf + col] = lo;
-      out[half_part(3) + col * kLeaf + row] = lo;
+      out[half_part(2) + rc] = lo;
+      out[half_part(3) + cr] = lo;
     }
     if (outm) {
-      outm[col * kLeaf + row] = hi;
-      outm[half_part(1) + row * kLeaf + col] = hi;
+      outm[cr] = hi;
+      outm[half_part(1) + rc] = hi;
       if (is_split(P)) {
-        outm[half_part(2) + col * kLeaf + row] = lo;
-        outm[half_part(3) + row * kLeaf + col] = lo;
+        outm[half_part(2) + cr] = lo;
+        outm[half_part(3) + rc] = lo;
       }
     }
     const double stored = double(decode_half_f<P>(hi, lo));
@@ -384,7 +385,7 @@ __global__ void __launch_bounds__(256) k_sp2_rest_half(RestArgs r) {
     const int el = q * 64 + lane;
     const double v = 2.0 * decode_half<P>(x[el], is_split(P) ? x[half_part(2) + el] : T(0.0f));
     nrm += v * v;
-    if (i == j && (el >> 5) == (el & 31)) tr += v;
+    if (i == j && half_idx_diag(el)) tr += v;
   }
   nrm = wave_sum(nrm);
   if (i == j) tr = wave_sum(tr);

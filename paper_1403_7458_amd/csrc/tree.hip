@@ -138,11 +138,12 @@ __global__ void __launch_bounds__(256) k_write_tiles_half(const double* __restri
     const int64_t r = int64_t(bi) * kLeaf + row, c = int64_t(bj) * kLeaf + col;
     T hi, lo;
     encode_half<P>((r < n && c < n) ? scaled(a, lda, r, c, sc) : 0.0, hi, lo);
-    tile[row * kLeaf + col] = hi;
-    tile[half_part(1) + col * kLeaf + row] = hi;
+    const int rc = half_idx(row, col), cr = half_idx(col, row);
+    tile[rc] = hi;
+    tile[half_part(1) + cr] = hi;
     if (is_split(P)) {
-      tile[half_part(2) + row * kLeaf + col] = lo;
-      tile[half_part(3) + col * kLeaf + row] = lo;
+      tile[half_part(2) + rc] = lo;
+      tile[half_part(3) + cr] = lo;
     }
     if (bi == bj && row == col) tr += decode_half<P>(hi, lo);
   }
@@ -173,8 +174,8 @@ __global__ void __launch_bounds__(256) k_to_dense_half(const void* __restrict__ 
     const int64_t r = int64_t(bi) * kLeaf + row, c = int64_t(bj) * kLeaf + col;
     if (r < n && c < n)
       out[r * ld + c] =
-          tile ? decode_half<P>(tile[row * kLeaf + col],
-                                is_split(P) ? tile[half_part(2) + row * kLeaf + col] : T(0.0f))
+          tile ? decode_half<P>(tile[half_idx(row, col)],
+                                is_split(P) ? tile[half_part(2) + half_idx(row, col)] : T(0.0f))
                : 0.0;
   }
 }
