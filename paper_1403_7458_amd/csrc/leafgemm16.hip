@@ -402,11 +402,10 @@ __global__ void __launch_bounds__(256) k_sp2_rest_half(RestArgs r) {
 // the kernels to fewer registers: the plain forms run three waves per SIMD
 // and the split forms two instead of one.  Measured: the extra waves win
 // while a single product is a few thousand groups (150 molecules, 3,481
-// groups: BF16 +13%, split FP16 +3%); with 10^5 groups (1000 molecules) the
+// groups: BF16 +22%, split FP16 +9%); with 10^5 groups (1000 molecules) the
 // look-ahead hides more of the operand fetch than the extra waves do (BF16
-// +5%, split FP16 +18%), and so it does in the batched launches of a serving
-// stream of mixed sizes (split FP16 +11% over one set, +7% over choosing by
-// the batch's group count).
+// +5%, split FP16 +16%), and so it does in the batched launches of a serving
+// stream of mixed sizes (split FP16 +7%).
 int half_ahead(int prec, int64_t groups, bool batched) {
   const char* v = std::getenv("SPAMM_HALF_AHEAD");
   if (v && std::strcmp(v, "1") == 0) return 1;
