@@ -401,8 +401,9 @@ __global__ void __launch_bounds__(256) k_sp2_rest_half(RestArgs r) {
 // of `groups` groups (SPAMM_HALF_AHEAD = 1 or 2 overrides).  One set holds
 // the kernels to fewer registers: the plain forms run three waves per SIMD
 // and the split forms two instead of one.  Measured: the extra waves win
-// while a single product is a few thousand groups (150 molecules, 3,481
-// groups: BF16 +22%, split FP16 +9%); with 10^5 groups (1000 molecules) the
+// while a single product is a few thousand groups (150 molecules, 1,770
+// groups per symmetric square: BF16 +22%, split FP16 +9%); with 10^5 groups
+// (1000 molecules) the
 // look-ahead hides more of the operand fetch than the extra waves do (BF16
 // +5%, split FP16 +16%), and so it does in the batched launches of a serving
 // stream of mixed sizes (split FP16 +7%).
