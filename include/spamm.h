@@ -165,7 +165,9 @@ int spamm_tree_build(const double* a, int64_t n, int64_t lda, int32_t prec, void
  * a, b:   handles of equal n and precision (SPAMM_ERR_SHAPE otherwise).
  * c:      new handle holding exactly the blocks with >= 1 executed product;
  *         its norm tree is that of the stored product.
- * st:     optional statistics.
+ * st:     optional statistics; NULL also skips the passes that only they
+ *         need (the non-zero pair count, the culled-product bound of the
+ *         top tiers).
  * Errors: SPAMM_ERR_INVALID_ARG (NULL handles, tau < 0 or not finite),
  *         SPAMM_ERR_SHAPE, SPAMM_ERR_OOM, SPAMM_ERR_DEVICE.
  */

@@ -226,12 +226,14 @@ def _stats_dict(st) -> dict:
     return {f: getattr(st, f) for f, _ in st._fields_ if f != "reserved"}
 
 
-def spamm_multiply(a: SpammMatrix, b: SpammMatrix, tau: float, stream=None):
+def spamm_multiply(a: SpammMatrix, b: SpammMatrix, tau: float, stream=None, stats: bool = True):
+    """(C, statistics dict); stats=False skips the passes only the
+    statistics need and returns (C, None)."""
     h = ctypes.c_void_p()
     st = MultStats()
     _check(load().spamm_multiply(a.handle, b.handle, float(tau), _stream(stream), ctypes.byref(h),
-                                 ctypes.byref(st)))
-    return SpammMatrix(h), _stats_dict(st)
+                                 ctypes.byref(st) if stats else None))
+    return SpammMatrix(h), (_stats_dict(st) if stats else None)
 
 
 def spamm_cull(a: SpammMatrix, b: SpammMatrix, tau: float, stream=None) -> dict:

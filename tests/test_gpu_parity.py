@@ -215,6 +215,10 @@ def test_multiply_is_deterministic(torch_dev, lib):
     c1 = lib.spamm_to_dense(lib.spamm_multiply(ma, ma, 1e-3)[0])
     c2 = lib.spamm_to_dense(lib.spamm_multiply(ma, ma, 1e-3)[0])
     np.testing.assert_array_equal(c1, c2)
+    # Without statistics: the same product (only the statistics passes go).
+    c3, st3 = lib.spamm_multiply(ma, ma, 1e-3, stats=False)
+    assert st3 is None
+    np.testing.assert_array_equal(lib.spamm_to_dense(c3), c1)
 
 
 def test_error_paths(torch_dev, lib):
