@@ -298,15 +298,18 @@ __global__ void __launch_bounds__(kTopThreads) k_cull_top(TopArgs g) {
     int r = 0;
     for (uint32_t m = mask; m; m &= m - 1) g.ks[to + r++] = __ffs(m) - 1;
   }
-  for (int o = kTopThreads / 2; o > 0; o >>= 1) {
-    if (tid < o) s_e[tid] += s_e[tid + o];
-    __syncthreads();
+  // (want_err is uniform: every thread takes the same branch.)
+  if (g.want_err) {
+    for (int o = kTopThreads / 2; o > 0; o >>= 1) {
+      if (tid < o) s_e[tid] += s_e[tid + o];
+      __syncthreads();
+    }
   }
   if (tid == 0) {
     g.nptr[tz] = tc;
     ctl->n_nodes[t0] = tz;
     ctl->n_tasks[t0] = tc;
-    ctl->err[1] = s_e[0];
+    ctl->err[1] = g.want_err ? s_e[0] : 0.0;
   }
 }
 
