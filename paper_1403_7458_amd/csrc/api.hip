@@ -316,8 +316,6 @@ void DevBuf::release(hipStream_t s) {
   bytes = 0;
 }
 
-bool profiling_on() { return g_prof_on; }
-
 PhaseTimer::PhaseTimer(int ph, hipStream_t s, int64_t prod) : phase(ph), stream(s), products(prod) {
   if (!g_prof_on || !(g_prof_mask >> ph & 1u)) return;
   start = take_event(current_device());

@@ -122,7 +122,6 @@ struct PhaseTimer {
   PhaseTimer(int ph, hipStream_t s, int64_t prod = 0);
   ~PhaseTimer();
 };
-bool profiling_on();
 
 }  // namespace spamm
 
